@@ -1,0 +1,201 @@
+"""CPU oracle of the CKKS hybrid KeySwitch: test infrastructure only.
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark
+use this package. It wraps ``ks_oracle.c`` (plain C, 128-bit products reduced
+with ``%``, textbook NTT loops, defining BConv sums) through ctypes, and
+``tiny.py`` holds a second, pure-Python oracle for tiny N built on the O(N^2)
+definition of the transform. Neither shares code with the GPU library.
+
+The operation follows the KeySwitch description in the paper's Background
+section (ModUp = iNTT -> BConv -> NTT per digit, KeyMult = multiply by the
+digit's evaluation key and sum over digits, ModDown = iNTT -> BConv -> NTT then
+subtract and divide by P). The choices the paper leaves open are listed in
+the header of ``ks_oracle.c``.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ks_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_i8p = np.ctypeslib.ndpointer(dtype=np.int8, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = True) -> str:
+    """Compile ks_oracle.c into liboracle.so with gcc (OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        c_int, c_u64 = ctypes.c_int, ctypes.c_uint64
+        L.orc_derive.argtypes = [c_int, c_int, c_int, _u64p, _u64p, _i64p]
+        L.orc_is_prime.argtypes = [c_u64]
+        L.orc_ntt.argtypes = [c_u64, c_u64, c_int, _u64p, c_int]
+        L.orc_intt.argtypes = [c_u64, c_u64, c_int, _u64p, c_int]
+        L.orc_bconv.argtypes = [c_int, c_int, c_int, c_int, _u64p, _u64p, c_int]
+        L.orc_modup.argtypes = [c_int, c_int, c_int, _u64p, _u64p, c_int]
+        L.orc_keymult.argtypes = [c_int, c_int, c_int, _u64p, _u64p, _u64p, c_int]
+        L.orc_moddown.argtypes = [c_int, c_int, c_int, _u64p, _u64p, c_int]
+        L.orc_keyswitch.argtypes = [c_int, c_int, c_int, _u64p, _u64p, _u64p, c_int]
+        L.orc_keygen.argtypes = [c_int, c_int, c_int, c_int, c_u64, c_u64, c_u64, c_u64, c_int,
+                                 _i8p, _i8p, _u64p]
+        L.orc_ks_error.argtypes = [c_int, c_int, c_int, _u64p, _u64p, _i8p, _i8p, _i64p, c_int]
+        L.orc_max_threads.restype = c_int
+        L.orc_set_threads.argtypes = [c_int]
+        _lib = L
+    return _lib
+
+
+class Params:
+    """Parameters of one (dnum, N, ell) set as the oracle derives them."""
+
+    def __init__(self, dnum: int, log_n: int, ell: int):
+        mod = np.zeros(256, dtype=np.uint64)
+        psi = np.zeros(256, dtype=np.uint64)
+        info = np.zeros(5, dtype=np.int64)
+        if lib().orc_derive(dnum, log_n, ell, mod, psi, info) != 0:
+            raise ValueError(f"invalid parameters dnum={dnum} log_n={log_n} ell={ell}")
+        self.dnum, self.log_n, self.ell = dnum, log_n, ell
+        self.n, _, self.k, self.alpha, self.ndig = (int(v) for v in info)
+        self.nl = self.ell + self.k
+        self.moduli = [int(v) for v in mod[: self.nl]]
+        self.psi = [int(v) for v in psi[: self.nl]]
+        self.q = self.moduli[: self.ell]
+        self.p = self.moduli[self.ell:]
+
+    def digit(self, j: int):
+        lo = j * self.alpha
+        return list(range(lo, min(lo + self.alpha, self.ell)))
+
+    def __repr__(self):
+        return f"Params(dnum={self.dnum}, N=2^{self.log_n}, ell={self.ell}, k={self.k})"
+
+
+def _c(a):
+    return np.ascontiguousarray(a, dtype=np.uint64)
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
+
+
+def set_threads(t: int) -> None:
+    lib().orc_set_threads(int(t))
+
+
+def is_prime(n: int) -> bool:
+    return bool(lib().orc_is_prime(n))
+
+
+def ntt(q: int, psi: int, log_n: int, a) -> np.ndarray:
+    """Forward negacyclic NTT of every length-N row of a (copy returned)."""
+    x = _c(a).copy()
+    lib().orc_ntt(q, psi, log_n, x, x.size >> log_n)
+    return x
+
+
+def intt(q: int, psi: int, log_n: int, a) -> np.ndarray:
+    x = _c(a).copy()
+    lib().orc_intt(q, psi, log_n, x, x.size >> log_n)
+    return x
+
+
+def bconv(P: Params, src_set: int, src, batch: int = 1) -> np.ndarray:
+    """Fast base conversion; src_set = digit j (-> PQ minus D_j) or -1 (P -> Q)."""
+    src = _c(src)
+    if src_set < 0:
+        nd = P.ell
+    else:
+        nd = P.nl - len(P.digit(src_set))
+    dst = np.zeros((batch, nd, P.n), dtype=np.uint64)
+    if lib().orc_bconv(P.dnum, P.log_n, P.ell, src_set, src, dst, batch) != 0:
+        raise ValueError("bconv")
+    return dst
+
+
+def modup(P: Params, d, batch: int) -> np.ndarray:
+    ext = np.zeros((batch, P.ndig, P.nl, P.n), dtype=np.uint64)
+    if lib().orc_modup(P.dnum, P.log_n, P.ell, _c(d), ext, batch) != 0:
+        raise ValueError("modup")
+    return ext
+
+
+def keymult(P: Params, ext, evk, batch: int) -> np.ndarray:
+    acc = np.zeros((batch, 2, P.nl, P.n), dtype=np.uint64)
+    if lib().orc_keymult(P.dnum, P.log_n, P.ell, _c(ext), _c(evk), acc, batch) != 0:
+        raise ValueError("keymult")
+    return acc
+
+
+def moddown(P: Params, acc, batch: int) -> np.ndarray:
+    out = np.zeros((batch, 2, P.ell, P.n), dtype=np.uint64)
+    if lib().orc_moddown(P.dnum, P.log_n, P.ell, _c(acc), out, batch) != 0:
+        raise ValueError("moddown")
+    return out
+
+
+def keyswitch(P: Params, d, evk, batch: int) -> np.ndarray:
+    out = np.zeros((batch, 2, P.ell, P.n), dtype=np.uint64)
+    if lib().orc_keyswitch(P.dnum, P.log_n, P.ell, _c(d), _c(evk), out, batch) != 0:
+        raise ValueError("keyswitch")
+    return out
+
+
+def keygen(P: Params, h: int = 64, seeds=(1, 2, 3, 4), noiseless: bool = False):
+    """(s, s2, evk): ternary secrets with h nonzeros and the key from s to s2."""
+    s = np.zeros(P.n, dtype=np.int8)
+    s2 = np.zeros(P.n, dtype=np.int8)
+    evk = np.zeros((P.ndig, 2, P.nl, P.n), dtype=np.uint64)
+    rc = lib().orc_keygen(P.dnum, P.log_n, P.ell, h, seeds[0], seeds[1], seeds[2], seeds[3],
+                          int(noiseless), s, s2, evk)
+    if rc != 0:
+        raise ValueError("keygen")
+    return s, s2, evk
+
+
+def ks_error(P: Params, d, out, s, s2, batch: int):
+    """(agree, err): err[b] is the decryption error of KS output b under s2
+    against d*s, as centered integers; agree says every limb gives the same."""
+    err = np.zeros((batch, P.n), dtype=np.int64)
+    rc = lib().orc_ks_error(P.dnum, P.log_n, P.ell, _c(d), _c(out), np.ascontiguousarray(s, np.int8),
+                            np.ascontiguousarray(s2, np.int8), err, batch)
+    if rc < 0:
+        raise ValueError("ks_error")
+    return bool(rc), err
+
+
+def ks_bound(P: Params, h: int, b_e: int = 19) -> int:
+    """Largest |e| a correct KeySwitch output may show when decrypted.
+
+    With E_j in [0, alpha*D_j) the ModUp lift of digit j, the KeySwitch output
+    decrypts to d*s + W - v0 - v1*s2 where
+    |W| <= sum_j N*alpha*D_j*B_e/P + 1 + h and 0 <= v_c < k, so
+    |e| < sum_j N*alpha*D_j*B_e/P + (1 + h)(1 + k)."""
+    from fractions import Fraction
+    Pbig = 1
+    for p in P.p:
+        Pbig *= p
+    first = Fraction(0)
+    for j in range(P.ndig):
+        Dj = 1
+        for i in P.digit(j):
+            Dj *= P.q[i]
+        first += Fraction(P.n * len(P.digit(j)) * Dj * b_e, Pbig)
+    import math
+    return math.floor(first) + (1 + h) * (1 + P.k)
