@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Throughput of the CKKS hybrid KeySwitch on one MI355X.
+
+One step = one batched KeySwitch (ModUp, KeyMult, ModDown for every
+ciphertext of the batch) through libks, with inputs already resident in HBM.
+Prints one JSON line: KeySwitch/s for the batch, the plain single-ciphertext
+rate beside it, per-step latency percentiles, the roofline of the dominant
+kernel (timed with HIP events inside the timed region) and the CPU oracle's
+rate on a bounded sample of the same workload.
+
+Inputs are synthetic (seeded SplitMix64): d uniform modulo each prime in NTT
+form, and a uniform stand-in evaluation key of the real key's shape (a real
+key is uniform modulo each prime as well).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# name: (dnum, log2 N, ell, batch, description)
+WORKLOADS = {
+    "c0": (2, 13, 6, 1, "plain KeySwitch (dnum,N,L)=(2,2^13,6)"),
+    "c1": (2, 15, 10, 32, "batched KeySwitch (dnum,N,L)=(2,2^15,10), batch 32, shared evk"),
+    "c2": (4, 16, 32, 8, "batched KeySwitch (dnum,N,L)=(4,2^16,32), batch 8, shared evk"),
+    "c3": (8, 17, 56, 2, "deep-circuit KeySwitch (dnum,N,L)=(8,2^17,56), batch 2"),
+}
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_bytes(G, plan, batch, kind):
+    """Algorithmic HBM bytes of one launch of `kind` under a one-chunk plan:
+    each input the kernel needs read once, each output written once."""
+    W, N, B = 8, G.n, batch
+    ell, nl, k, nd, a = G.ell, G.nl, G.k, G.ndig, G.alpha
+    if kind == 0:    # inverse block pass of d
+        return 2 * B * ell * N * W
+    if kind == 1:    # ModUp columns: read the digits, write the raised limbs
+        return B * ell * N * W + B * sum(nl - len(range(j * a, min((j + 1) * a, ell))) for j in range(nd)) * N * W
+    if kind == 2:    # block pass + KeyMult: raised limbs and d in, key in once, acc out
+        ext = B * sum(nl - len(range(j * a, min((j + 1) * a, ell))) for j in range(nd)) * N * W
+        return ext + B * ell * N * W + 2 * nd * nl * N * W + 2 * B * nl * N * W
+    if kind == 3:    # ModDown columns: P limbs in, Q limbs out
+        return 2 * B * k * N * W + 2 * B * ell * N * W
+    if kind == 4:    # ModDown blocks: t2 and acc_Q in, out written
+        return 3 * 2 * B * ell * N * W
+    return None
+
+
+def percentile(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    i = min(len(xs) - 1, max(0, int(round(p / 100.0 * (len(xs) - 1)))))
+    return xs[i]
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--batch", type=int, default=0, help="override the workload's batch size")
+    ap.add_argument("--plan", default="", help="dataflow[,chunks[,log_r]] e.g. DPOB or DSOC,2,3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(batch sharding across GPUs is described in DESIGN.md but not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2603_16692_amd as ks
+    from synth import ciphertext_batch, uniform_key
+
+    dnum, log_n, ell, batch, desc = WORKLOADS[args.workload]
+    if args.batch:
+        batch = args.batch
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    G = ks.KsParams(dnum, log_n, ell)
+
+    plan = None
+    if args.plan:
+        parts = args.plan.split(",")
+        df = {"DSOB": ks.DSOB, "DPOB": ks.DPOB, "DSOC": ks.DSOC, "DPOC": ks.DPOC, "STAGED": ks.STAGED}[parts[0]]
+        chunks = int(parts[1]) if len(parts) > 1 else 1
+        log_r = int(parts[2]) if len(parts) > 2 else 0
+        plan = ks.make_plan(df, chunks, log_r)
+    else:
+        plan = G.default_plan(batch)
+
+    to_dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda")
+    d = to_dev(ciphertext_batch(G.moduli[:ell], G.n, batch))
+    evk = to_dev(uniform_key(G.moduli, G.n, G.ndig))
+    out = torch.empty((batch, 2, ell, G.n), dtype=torch.int64, device="cuda")
+    ws = G.workspace(batch, plan)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        G.keyswitch(d, evk, out, batch, ws, plan)
+    torch.cuda.synchronize()
+
+    # per-kernel breakdown of one step (untimed) -> the dominant kernel kind
+    ev = ks.HipEvents(2 * 256)
+    ks.trace_begin(ev)
+    G.keyswitch(d, evk, out, batch, ws, plan)
+    kinds = ks.trace_end()
+    torch.cuda.synchronize()
+    per_kind = {}
+    for i, kd in enumerate(kinds):
+        per_kind[kd] = per_kind.get(kd, 0.0) + ev.elapsed_ms(2 * i, 2 * i + 1)
+    dominant = max(per_kind, key=per_kind.get)
+
+    # timed region: K steps; step boundaries and every launch of the dominant
+    # kernel are bracketed by HIP events on the stream the kernels run on
+    step_ev = ks.HipEvents(args.steps + 1)
+    per_step = sum(1 for k in kinds if k == dominant)
+    kev = ks.HipEvents(2 * args.steps * per_step)
+    torch.cuda.synchronize()
+    ks.trace_begin(kev, 1 << dominant)
+    t0 = time.perf_counter()
+    step_ev.record(0, stream)
+    for i in range(args.steps):
+        G.keyswitch(d, evk, out, batch, ws, plan)
+        step_ev.record(i + 1, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dom_kinds = ks.trace_end(kev.count // 2)
+    step_ms = [step_ev.elapsed_ms(i, i + 1) for i in range(args.steps)]
+    total_ms = step_ev.elapsed_ms(0, args.steps)
+    dom_ms = [kev.elapsed_ms(2 * i, 2 * i + 1) for i in range(len(dom_kinds))]
+    ms_per_step = total_ms / args.steps
+    value = batch * args.steps / (total_ms / 1e3)
+
+    # plain single-ciphertext path on the same parameters (default plan)
+    plain = None
+    if batch > 1:
+        d1 = d[:1].contiguous()
+        out1 = out[:1].contiguous()
+        ws1 = G.workspace(1)
+        for _ in range(3):
+            G.keyswitch(d1, evk, out1, 1, ws1)
+        pe = ks.HipEvents(2)
+        reps = max(10, args.steps)
+        pe.record(0, stream)
+        for _ in range(reps):
+            G.keyswitch(d1, evk, out1, 1, ws1)
+        pe.record(1, stream)
+        torch.cuda.synchronize()
+        plain = reps / (pe.elapsed_ms(0, 1) / 1e3)
+
+    # roofline of the dominant kernel: its algorithmic bytes per step over its
+    # time per step (= per launch bytes over the average launch time)
+    dom_avg_ms = sum(dom_ms) / len(dom_ms)
+    nbytes = kernel_bytes(G, plan, batch, dominant)
+    roofline = None
+    if nbytes is not None:
+        per_launch = nbytes / per_step
+        achieved = per_launch / (dom_avg_ms / 1e3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": ks.KIND_NAMES[dominant], "kernel_avg_ms": round(dom_avg_ms, 4),
+                    "launches_per_step": per_step, "algorithmic_bytes_per_launch": int(per_launch)}
+
+    # algorithmic bytes of the whole KeySwitch: d + out + evk / batch
+    ks_bytes = (ell * G.n * 8) + (2 * ell * G.n * 8) + (2 * G.ndig * G.nl * G.n * 8) / batch
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        P = oracle.Params(dnum, log_n, ell)
+        dh = ciphertext_batch(P.q, P.n, 1)
+        kh = uniform_key(P.moduli, P.n, P.ndig)
+        n_done, t_start = 0, time.perf_counter()
+        while True:
+            oracle.keyswitch(P, dh, kh, 1)
+            n_done += 1
+            el = time.perf_counter() - t_start
+            if el >= args.cpu_seconds or el / n_done * (n_done + 1) > 3 * args.cpu_seconds:
+                break
+        cpu = {"value": round(n_done / el, 4), "unit": "KeySwitch/s", "cores": oracle.max_threads(),
+               "kind": "oracle",
+               "sample": f"{n_done} single-ciphertext KeySwitch(es) of the same parameter set, {el:.1f} s"}
+
+    line = {
+        "metric": "KeySwitch/s", "value": round(value, 2), "unit": "KeySwitch/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": desc, "dnum": dnum, "N": G.n, "L": ell, "k": G.k, "batch": batch,
+                   "plan": repr(plan), "launches_per_step": len(kinds)},
+        "plain_single_ks_per_s": round(plain, 2) if plain else None,
+        "latency_ms": {"p50": round(percentile(step_ms, 50), 4), "p99": round(percentile(step_ms, 99), 4)},
+        "ks_algorithmic_GBs": round(ks_bytes * value / 1e9, 1),
+        "breakdown_ms": {ks.KIND_NAMES[k]: round(v, 4) for k, v in sorted(per_kind.items())},
+        "wall_s": round(t1 - t0, 4),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,167 @@
+/*
+ * ks.h - C ABI of the MI355X (gfx950) CKKS hybrid KeySwitch library (libks.so).
+ *
+ * KeySwitch turns a polynomial d, given over the RNS basis Q = q_0..q_{ell-1}
+ * in NTT form, into a pair (out_0, out_1) over Q such that
+ * out_0 + out_1*s2 ~ d*s, given an evaluation key from s to s2 (Background
+ * section of the paper, "KeySwitch" subsection, and its Fig. 1):
+ *   ModUp   : split d into dnum digits of alpha limbs; raise each digit to the
+ *             basis PQ by iNTT -> BConv -> NTT;
+ *   KeyMult : multiply each raised digit by its key pair and sum over digits;
+ *   ModDown : bring the sum back to Q by iNTT -> BConv -> NTT, subtract, and
+ *             multiply by P^-1.
+ * The order of the work (digit-serial or digit-parallel, output bulk or
+ * chunked: the dataflow classification of the paper's Qualitative Analysis
+ * section, Table III) is chosen by a ks_plan; every plan gives bit-identical
+ * results.
+ *
+ * Conventions shared by every call:
+ *   - Parameters: Q holds ell primes q < 2^50 and P holds k = alpha primes
+ *     p < 2^60, all = 1 (mod 2N), the largest such primes in descending order;
+ *     alpha = ceil(ell/dnum); digit j holds Q limbs [j*alpha, min((j+1)*alpha, ell)),
+ *     and there are ndig = ceil(ell/alpha) digits. The extended basis is
+ *     q_0..q_{ell-1}, p_0..p_{k-1} (limb index 0..ell+k-1).
+ *   - Transform: NTT(a)[t] = sum_i a_i psi^(i*(2*brv(t)+1)) mod q with psi the
+ *     smallest primitive 2N-th root of unity mod q (negacyclic ring
+ *     Z_q[x]/(x^N+1), bit-reversed evaluation order). INTT is its inverse,
+ *     including the factor N^-1.
+ *   - BConv is the fast conversion without overflow correction:
+ *     z_t = sum_i [x_i * (S/s_i)^-1]_{s_i} * (S/s_i) mod t.
+ *   - Data: canonical residues in [0, modulus) stored as uint64, limb-major,
+ *     coefficient index fastest. Every data pointer is a device pointer owned
+ *     by the caller and aligned to 256 bytes; the library never frees it.
+ *     Inputs that are not canonical residues give unspecified (but in-bounds)
+ *     results.
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *     stream). Every call only enqueues work on it and returns without
+ *     synchronising; enqueued work may be captured into a HIP graph.
+ *   - Errors: every int-returning call returns KS_OK (0) or a negative code;
+ *     nothing is enqueued when a call fails. No exception crosses the ABI.
+ */
+#ifndef KS_H
+#define KS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KS_OK 0
+#define KS_EINVAL -1  /* a size or parameter is out of range */
+#define KS_ENULL -2   /* a required pointer is NULL */
+#define KS_EALIGN -3  /* a data pointer is not 256-byte aligned */
+#define KS_ENOMEM -4  /* the library could not allocate its tables */
+#define KS_EUNSUP -5  /* the plan is not valid for these parameters */
+#define KS_EHIP -6    /* a HIP call failed; ks_last_hip_error() tells which */
+
+#define KS_MAX_LIMBS 128 /* ell + k */
+#define KS_SET_P (-1)    /* ks_bconv source set: the P primes (target: Q) */
+
+/* Dataflows of the paper's classification (Qualitative Analysis section). */
+#define KS_DSOB 0 /* digits one after another, all output limbs at once */
+#define KS_DPOB 1 /* all digits in one launch per stage, all output limbs */
+#define KS_DSOC 2 /* digits one after another, output limbs in `chunks` parts */
+#define KS_DPOC 3 /* all digits per launch, output limbs in `chunks` parts */
+#define KS_STAGED 4 /* ks_modup, ks_keymult and ks_moddown in sequence */
+
+typedef struct ks_params ks_params; /* opaque, immutable after creation */
+
+typedef struct {
+  int dataflow; /* KS_DSOB .. KS_STAGED */
+  int chunks;   /* output partitions for KS_DSOC / KS_DPOC (1..64), else ignored */
+  int log_r;    /* NTT split N = 2^log_r * M (rows per column pass), 0 = default */
+  int flags;    /* reserved, must be 0 */
+} ks_plan;
+
+typedef struct {
+  int n, log_n, ell, k, alpha, dnum, ndig;
+  uint64_t moduli[KS_MAX_LIMBS]; /* q_0..q_{ell-1}, p_0..p_{k-1} */
+  uint64_t psi[KS_MAX_LIMBS];
+} ks_info;
+
+/* Derive primes, roots, twiddle tables and BConv constants for (dnum, N =
+ * 2^log_n, ell) and upload them to the current HIP device. 3 <= log_n <= 17,
+ * 1 <= dnum <= ell, ell + ceil(ell/dnum) <= KS_MAX_LIMBS. The handle is
+ * immutable and may be shared by threads and streams of that device.
+ * Synchronous (it uploads tables). */
+int ks_params_create(int dnum, int log_n, int ell, ks_params** out);
+void ks_params_destroy(ks_params* p);
+
+/* Host copy of the derived parameters. */
+int ks_params_info(const ks_params* p, ks_info* info);
+
+/* Device workspace (bytes) that ks_keyswitch needs for `batch` ciphertexts
+ * under `plan` (NULL = default plan); ks_modup and ks_moddown need
+ * ks_workspace_bytes(p, batch, &{KS_STAGED}). */
+int ks_workspace_bytes(const ks_params* p, int batch, const ks_plan* plan, size_t* bytes);
+
+/* Default plan for these parameters and batch size. */
+int ks_default_plan(const ks_params* p, int batch, ks_plan* plan);
+
+/* In-place forward / inverse NTT of x [batch][n_limbs][N]; limb r of each item
+ * uses extended-basis prime basis_first + r. */
+int ks_ntt(const ks_params* p, uint64_t* x, int basis_first, int n_limbs, int batch, void* stream);
+int ks_intt(const ks_params* p, uint64_t* x, int basis_first, int n_limbs, int batch, void* stream);
+
+/* Fast base conversion in coefficient form. src_set = digit j: src
+ * [batch][|D_j|][N] over D_j -> dst [batch][ell+k-|D_j|][N] over the other limbs
+ * of PQ in basis order. src_set = KS_SET_P: src [batch][k][N] over P -> dst
+ * [batch][ell][N] over Q. */
+int ks_bconv(const ks_params* p, const uint64_t* src, int src_set, uint64_t* dst, int batch, void* stream);
+
+/* ModUp: d [batch][ell][N] (NTT form) -> ext [batch][ndig][ell+k][N] (NTT
+ * form); on digit j's own limbs ext holds d unchanged. */
+int ks_modup(const ks_params* p, const uint64_t* d, uint64_t* ext, int batch, void* ws, void* stream);
+
+/* KeyMult: acc[b][c][t] = sum_j ext[b][j][t] * evk[j][c][t] mod t for c = 0, 1.
+ * evk [ndig][2][ell+k][N] (component 0 = b, 1 = a) is shared by the batch;
+ * acc [batch][2][ell+k][N]. */
+int ks_keymult(const ks_params* p, const uint64_t* ext, const uint64_t* evk, uint64_t* acc, int batch,
+               void* stream);
+
+/* ModDown: acc [batch][2][ell+k][N] -> out [batch][2][ell][N] with
+ * out_c = (acc_c,Q - NTT(BConv_{P->Q}(INTT(acc_c,P)))) * P^-1. acc is not modified. */
+int ks_moddown(const ks_params* p, const uint64_t* acc, uint64_t* out, int batch, void* ws, void* stream);
+
+/* The whole KeySwitch: d [batch][ell][N] -> out [batch][2][ell][N], with the
+ * key evk [ndig][2][ell+k][N]. plan NULL = ks_default_plan. ws must hold
+ * ks_workspace_bytes(p, batch, plan) bytes. d, evk and out must not overlap ws. */
+int ks_keyswitch(const ks_params* p, const uint64_t* d, const uint64_t* evk, uint64_t* out, int batch,
+                 const ks_plan* plan, void* ws, void* stream);
+
+/* Number of kernel launches ks_keyswitch enqueues for (batch, plan). */
+int ks_launch_count(const ks_params* p, int batch, const ks_plan* plan);
+
+/* Kernel kinds of the launch trace. */
+#define KS_K_INTT_D 0         /* inverse block pass of d (first step of ModUp) */
+#define KS_K_MODUP_COLS 1     /* ModUp: inverse column pass, BConv, forward column pass */
+#define KS_K_KEYMULT_BLOCKS 2 /* forward block pass of the raised digits + KeyMult */
+#define KS_K_MODDOWN_COLS 3   /* ModDown: inverse column pass, BConv, forward column pass */
+#define KS_K_MODDOWN_BLOCKS 4 /* forward block pass + subtraction and P^-1 */
+#define KS_K_EXT_BLOCKS 5     /* ks_modup: forward block pass of ext */
+#define KS_K_PBLOCKS_INV 6    /* ks_moddown: inverse block pass of the P limbs */
+#define KS_K_COPY_DIGITS 7    /* ks_modup: digit limbs copied into ext */
+#define KS_K_KEYMULT 8        /* ks_keymult element-wise kernel */
+#define KS_K_BCONV 9          /* ks_bconv */
+#define KS_K_NTT 10           /* ks_ntt / ks_intt passes */
+
+/* Launch trace (profiling; eager calls only, never under graph capture).
+ * After ks_trace_begin, every kernel launch of a kind whose bit is set in
+ * kind_mask that this thread enqueues through the library is bracketed by
+ * hipEventRecord(events[2i]) and hipEventRecord(events[2i+1]) on its stream,
+ * for i = 0 .. capacity-1. `events` holds 2*capacity hipEvent_t created by the
+ * caller (as void*). ks_trace_end stops recording, writes the kind of each
+ * recorded launch to kinds[0 .. min(n, capacity)-1] and returns n. */
+int ks_trace_begin(void** events, int capacity, unsigned kind_mask);
+int ks_trace_end(int* kinds, int capacity);
+
+const char* ks_strerror(int code);
+/* Name of the HIP error behind the calling thread's last KS_EHIP. */
+const char* ks_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KS_H */

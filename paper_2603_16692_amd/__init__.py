@@ -1,0 +1,254 @@
+"""MI355X (gfx950) CKKS hybrid KeySwitch: Python binding of libks.so.
+
+The binding only marshals arguments: every step of the path runs in the HIP
+kernels of ``libks.so`` (see ``include/ks.h`` for the contract of each
+call). Tensors are torch device tensors of dtype int64 holding the uint64
+residues (every residue is below 2^60, so the bit patterns agree); torch
+supplies device memory and the HIP stream. There is no CPU fallback: if the
+library is missing, importing this package raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libks.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build the HIP library first "
+        "(python -c 'import __graft_entry__ as g; g.build()')")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+KS_OK, KS_EINVAL, KS_ENULL, KS_EALIGN, KS_ENOMEM, KS_EUNSUP, KS_EHIP = 0, -1, -2, -3, -4, -5, -6
+KS_MAX_LIMBS = 128
+KS_SET_P = -1
+DSOB, DPOB, DSOC, DPOC, STAGED = 0, 1, 2, 3, 4
+DATAFLOW_NAMES = {DSOB: "DSOB", DPOB: "DPOB", DSOC: "DSOC", DPOC: "DPOC", STAGED: "STAGED"}
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("dataflow", ctypes.c_int), ("chunks", ctypes.c_int), ("log_r", ctypes.c_int),
+                ("flags", ctypes.c_int)]
+
+    def __repr__(self):
+        return f"Plan({DATAFLOW_NAMES.get(self.dataflow, self.dataflow)}, chunks={self.chunks}, log_r={self.log_r})"
+
+    def key(self):
+        return (self.dataflow, self.chunks, self.log_r)
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("log_n", ctypes.c_int), ("ell", ctypes.c_int), ("k", ctypes.c_int),
+                ("alpha", ctypes.c_int), ("dnum", ctypes.c_int), ("ndig", ctypes.c_int),
+                ("moduli", ctypes.c_uint64 * KS_MAX_LIMBS), ("psi", ctypes.c_uint64 * KS_MAX_LIMBS)]
+
+
+_vp, _i, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+_lib.ks_params_create.argtypes = [_i, _i, _i, ctypes.POINTER(_vp)]
+_lib.ks_params_destroy.argtypes = [_vp]
+_lib.ks_params_destroy.restype = None
+_lib.ks_params_info.argtypes = [_vp, ctypes.POINTER(Info)]
+_lib.ks_workspace_bytes.argtypes = [_vp, _i, ctypes.POINTER(Plan), ctypes.POINTER(_sz)]
+_lib.ks_default_plan.argtypes = [_vp, _i, ctypes.POINTER(Plan)]
+_lib.ks_ntt.argtypes = [_vp, _vp, _i, _i, _i, _vp]
+_lib.ks_intt.argtypes = [_vp, _vp, _i, _i, _i, _vp]
+_lib.ks_bconv.argtypes = [_vp, _vp, _i, _vp, _i, _vp]
+_lib.ks_modup.argtypes = [_vp, _vp, _vp, _i, _vp, _vp]
+_lib.ks_keymult.argtypes = [_vp, _vp, _vp, _vp, _i, _vp]
+_lib.ks_moddown.argtypes = [_vp, _vp, _vp, _i, _vp, _vp]
+_lib.ks_keyswitch.argtypes = [_vp, _vp, _vp, _vp, _i, ctypes.POINTER(Plan), _vp, _vp]
+_lib.ks_launch_count.argtypes = [_vp, _i, ctypes.POINTER(Plan)]
+_lib.ks_strerror.argtypes = [_i]
+_lib.ks_strerror.restype = ctypes.c_char_p
+_lib.ks_last_hip_error.restype = ctypes.c_char_p
+
+_lib.ks_trace_begin.argtypes = [ctypes.POINTER(_vp), _i, ctypes.c_uint]
+_lib.ks_trace_end.argtypes = [ctypes.POINTER(_i), _i]
+
+KIND_NAMES = ["intt_d_blocks", "modup_cols", "keymult_blocks", "moddown_cols", "moddown_blocks", "ext_blocks",
+              "pblocks_inv", "copy_digits", "keymult", "bconv", "ntt"]
+
+EXPORTED = ["ks_params_create", "ks_params_destroy", "ks_params_info", "ks_workspace_bytes", "ks_default_plan",
+            "ks_ntt", "ks_intt", "ks_bconv", "ks_modup", "ks_keymult", "ks_moddown", "ks_keyswitch",
+            "ks_launch_count", "ks_strerror", "ks_last_hip_error", "ks_trace_begin", "ks_trace_end"]
+
+
+class KsError(RuntimeError):
+    def __init__(self, code, what):
+        msg = _lib.ks_strerror(code).decode()
+        if code == KS_EHIP:
+            msg += f" ({_lib.ks_last_hip_error().decode()})"
+        super().__init__(f"{what}: {msg} [{code}]")
+        self.code = code
+
+
+def _check(rc, what):
+    if rc != KS_OK:
+        raise KsError(rc, what)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_plan(dataflow=DPOB, chunks=1, log_r=0):
+    return Plan(dataflow, chunks, log_r, 0)
+
+
+class KsParams:
+    """Handle of one (dnum, N = 2^log_n, ell) parameter set on the current device."""
+
+    def __init__(self, dnum: int, log_n: int, ell: int):
+        h = _vp()
+        _check(_lib.ks_params_create(dnum, log_n, ell, ctypes.byref(h)), "ks_params_create")
+        self._h = h
+        info = Info()
+        _check(_lib.ks_params_info(h, ctypes.byref(info)), "ks_params_info")
+        self.n, self.log_n, self.ell, self.k = info.n, info.log_n, info.ell, info.k
+        self.alpha, self.dnum, self.ndig = info.alpha, info.dnum, info.ndig
+        self.nl = self.ell + self.k
+        self.moduli = [int(info.moduli[t]) for t in range(self.nl)]
+        self.psi = [int(info.psi[t]) for t in range(self.nl)]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.ks_params_destroy(h)
+            self._h = None
+
+    def __repr__(self):
+        return f"KsParams(dnum={self.dnum}, N=2^{self.log_n}, ell={self.ell}, k={self.k})"
+
+    # ------------------------------------------------------------ queries
+    def default_plan(self, batch: int = 1) -> Plan:
+        p = Plan()
+        _check(_lib.ks_default_plan(self._h, batch, ctypes.byref(p)), "ks_default_plan")
+        return p
+
+    def workspace_bytes(self, batch: int, plan: Plan = None) -> int:
+        b = _sz()
+        _check(_lib.ks_workspace_bytes(self._h, batch, ctypes.byref(plan) if plan else None, ctypes.byref(b)),
+               "ks_workspace_bytes")
+        return int(b.value)
+
+    def workspace(self, batch: int, plan: Plan = None, device="cuda") -> torch.Tensor:
+        nbytes = max(self.workspace_bytes(batch, plan), 8)
+        return torch.empty((nbytes + 7) // 8, dtype=torch.int64, device=device)
+
+    def launch_count(self, batch: int, plan: Plan = None) -> int:
+        rc = _lib.ks_launch_count(self._h, batch, ctypes.byref(plan) if plan else None)
+        if rc < 0:
+            raise KsError(rc, "ks_launch_count")
+        return rc
+
+    # -------------------------------------------------------------- calls
+    def ntt(self, x, basis_first=0, n_limbs=None, batch=None, stream=None):
+        n_limbs = x.shape[-2] if n_limbs is None else n_limbs
+        batch = (x.numel() // (n_limbs * self.n)) if batch is None else batch
+        _check(_lib.ks_ntt(self._h, _ptr(x), basis_first, n_limbs, batch, _stream(stream)), "ks_ntt")
+
+    def intt(self, x, basis_first=0, n_limbs=None, batch=None, stream=None):
+        n_limbs = x.shape[-2] if n_limbs is None else n_limbs
+        batch = (x.numel() // (n_limbs * self.n)) if batch is None else batch
+        _check(_lib.ks_intt(self._h, _ptr(x), basis_first, n_limbs, batch, _stream(stream)), "ks_intt")
+
+    def bconv(self, src, src_set, dst, batch, stream=None):
+        _check(_lib.ks_bconv(self._h, _ptr(src), src_set, _ptr(dst), batch, _stream(stream)), "ks_bconv")
+
+    def modup(self, d, ext, batch, ws, stream=None):
+        _check(_lib.ks_modup(self._h, _ptr(d), _ptr(ext), batch, _ptr(ws), _stream(stream)), "ks_modup")
+
+    def keymult(self, ext, evk, acc, batch, stream=None):
+        _check(_lib.ks_keymult(self._h, _ptr(ext), _ptr(evk), _ptr(acc), batch, _stream(stream)), "ks_keymult")
+
+    def moddown(self, acc, out, batch, ws, stream=None):
+        _check(_lib.ks_moddown(self._h, _ptr(acc), _ptr(out), batch, _ptr(ws), _stream(stream)), "ks_moddown")
+
+    def keyswitch(self, d, evk, out, batch, ws, plan: Plan = None, stream=None):
+        _check(_lib.ks_keyswitch(self._h, _ptr(d), _ptr(evk), _ptr(out), batch,
+                                 ctypes.byref(plan) if plan else None, _ptr(ws), _stream(stream)), "ks_keyswitch")
+
+    # ------------------------------------------------------------ helpers
+    def shapes(self, batch: int):
+        n, ell, nl, nd = self.n, self.ell, self.nl, self.ndig
+        return {"d": (batch, ell, n), "ext": (batch, nd, nl, n), "evk": (nd, 2, nl, n),
+                "acc": (batch, 2, nl, n), "out": (batch, 2, ell, n)}
+
+
+class HipEvents:
+    """A pool of HIP timing events, created through the HIP runtime."""
+
+    _hip = None
+
+    @staticmethod
+    def runtime():
+        if HipEvents._hip is None:
+            h = ctypes.CDLL("libamdhip64.so")
+            h.hipEventCreate.argtypes = [ctypes.POINTER(_vp)]
+            h.hipEventDestroy.argtypes = [_vp]
+            h.hipEventRecord.argtypes = [_vp, _vp]
+            h.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), _vp, _vp]
+            HipEvents._hip = h
+        return HipEvents._hip
+
+    def __init__(self, count: int):
+        h = HipEvents.runtime()
+        self.ev = (_vp * count)()
+        self.count = 0
+        for i in range(count):
+            e = _vp()
+            rc = h.hipEventCreate(ctypes.byref(e))
+            if rc != 0:
+                raise RuntimeError(f"hipEventCreate failed ({rc})")
+            self.ev[i] = e.value
+            self.count = i + 1
+
+    def record(self, i: int, stream=None) -> None:
+        rc = HipEvents._hip.hipEventRecord(self.ev[i], _stream(stream))
+        if rc != 0:
+            raise RuntimeError(f"hipEventRecord failed ({rc})")
+
+    def elapsed_ms(self, i: int, j: int) -> float:
+        ms = ctypes.c_float()
+        rc = HipEvents._hip.hipEventElapsedTime(ctypes.byref(ms), self.ev[i], self.ev[j])
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed ({rc})")
+        return float(ms.value)
+
+    def __del__(self):
+        h = HipEvents._hip
+        if h is not None:
+            for i in range(getattr(self, "count", 0)):
+                h.hipEventDestroy(self.ev[i])
+
+
+def trace_begin(events: HipEvents, kind_mask: int = 0xFFFFFFFF) -> None:
+    """Bracket the following kernel launches of the chosen kinds with events[2i], events[2i+1]."""
+    _check(_lib.ks_trace_begin(ctypes.cast(events.ev, ctypes.POINTER(_vp)), events.count // 2, kind_mask),
+           "ks_trace_begin")
+
+
+def trace_end(capacity: int = 4096):
+    """Stop tracing; returns the kind of every recorded launch, in order."""
+    kinds = (_i * capacity)()
+    n = _lib.ks_trace_end(kinds, capacity)
+    return [int(kinds[i]) for i in range(min(n, capacity))]
+
+
+def raw_call(name, *args):
+    """Direct access to an exported symbol (tests of the argument checks)."""
+    return getattr(_lib, name)(*args)

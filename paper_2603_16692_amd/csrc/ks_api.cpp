@@ -1,0 +1,446 @@
+// C ABI of libks (include/ks.h): parameter handles, argument checks, and the
+// plan executor that orders the kernels of one KeySwitch by dataflow
+// (DSOB, DPOB, DSOC, DPOC of the paper's classification, or the staged
+// ModUp / KeyMult / ModDown sequence).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ks.h"
+#include "ks_host.hpp"
+#include "ks_kernels.hpp"
+
+struct ks_params {
+  ks::HostParams hp;
+  ks::DevTables tb;
+  void* blob = nullptr;
+  int device = 0;
+};
+
+namespace {
+
+thread_local std::string g_hip_error = "none";
+
+// Launch trace of the calling thread (ks_trace_begin / ks_trace_end).
+struct Trace {
+  bool active = false;
+  hipEvent_t* events = nullptr;
+  int cap = 0, n = 0;
+  unsigned mask = 0;
+  std::vector<int> kinds;
+};
+thread_local Trace g_trace;
+
+// Runs one launch, bracketed by trace events when tracing is on for `kind`.
+template <class F>
+hipError_t traced(int kind, hipStream_t s, F&& launch) {
+  Trace& t = g_trace;
+  const bool rec = t.active && ((t.mask >> kind) & 1u) && t.n < t.cap;
+  if (rec) {
+    const hipError_t e = hipEventRecord(t.events[2 * t.n], s);
+    if (e != hipSuccess) return e;
+  }
+  const hipError_t e = launch();
+  if (rec && e == hipSuccess) {
+    const hipError_t e2 = hipEventRecord(t.events[2 * t.n + 1], s);
+    if (e2 != hipSuccess) return e2;
+    t.kinds.push_back(kind);
+    ++t.n;
+  }
+  return e;
+}
+
+int hip_fail(hipError_t e) {
+  g_hip_error = hipGetErrorName(e);
+  return KS_EHIP;
+}
+
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+int check_ptr(const void* p) {
+  if (!p) return KS_ENULL;
+  if (!aligned(p)) return KS_EALIGN;
+  return KS_OK;
+}
+
+int default_log_r(int log_n) { return log_n > 13 ? log_n - 13 : 0; }
+
+constexpr size_t kLdsBytes = 160 * 1024;
+constexpr int kColThreads = 64;
+
+// Plan validity for these parameters: the NTT split must be compiled and the
+// BConv staging of the column kernels must fit in LDS.
+int resolve_plan(const ks_params* p, const ks_plan* in, ks_plan& out) {
+  if (in) {
+    out = *in;
+  } else {
+    out = ks_plan{KS_DPOB, 1, 0, 0};
+  }
+  if (out.flags != 0) return KS_EUNSUP;
+  if (out.dataflow < KS_DSOB || out.dataflow > KS_STAGED) return KS_EUNSUP;
+  if (out.log_r == 0) out.log_r = default_log_r(p->hp.log_n);
+  if (out.log_r < 0) out.log_r = 0;
+  const int log_m = p->hp.log_n - out.log_r;
+  if (out.log_r > 4 || log_m < 3 || log_m > 14) return KS_EUNSUP;
+  const size_t R = (size_t)1 << out.log_r;
+  const size_t stage = (size_t)std::max(p->hp.alpha, p->hp.k) * R * kColThreads * sizeof(uint64_t);
+  if (stage > kLdsBytes) return KS_EUNSUP;
+  if (out.dataflow == KS_DSOC || out.dataflow == KS_DPOC) {
+    if (out.chunks < 1 || out.chunks > 64 || out.chunks > p->hp.ell) return KS_EUNSUP;
+  } else {
+    out.chunks = 1;
+  }
+  return KS_OK;
+}
+
+size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t t1, ext1, acc, t2, accp, ext, total;
+  int nslots;
+};
+
+// Workspace layout of one KeySwitch under `plan` for `batch` items.
+Layout layout(const ks_params* p, int batch, const ks_plan& plan) {
+  const size_t N = p->hp.n, B = (size_t)batch, W = sizeof(uint64_t);
+  const size_t ell = p->hp.ell, nl = p->hp.nl;
+  Layout L{};
+  if (plan.dataflow == KS_STAGED) {
+    // [ext][acc][scratch = max(t1, accp + t2)]
+    L.ext = 0;
+    L.acc = up256(B * p->hp.ndig * nl * N * W);
+    const size_t scratch = L.acc + up256(B * 2 * nl * N * W);
+    L.t1 = scratch;
+    L.accp = scratch;
+    L.t2 = scratch + up256(B * 2 * nl * N * W);
+    L.total = std::max(L.t1 + up256(B * ell * N * W), L.t2 + up256(B * 2 * ell * N * W));
+    return L;
+  }
+  const bool dp = plan.dataflow == KS_DPOB || plan.dataflow == KS_DPOC;
+  L.nslots = dp ? p->hp.ndig : 1;
+  L.t1 = 0;
+  L.ext1 = L.t1 + up256(B * ell * N * W);
+  L.acc = L.ext1 + up256(B * L.nslots * nl * N * W);
+  L.t2 = L.acc + up256(B * 2 * nl * N * W);
+  L.total = L.t2 + up256(B * 2 * ell * N * W);
+  return L;
+}
+
+void chunk_range(int n, int c, int i, int& a, int& b) {
+  a = (int)((long)n * i / c);
+  b = (int)((long)n * (i + 1) / c);
+}
+
+#define KS_TRY(x)                          \
+  do {                                     \
+    hipError_t e_ = (x);                   \
+    if (e_ != hipSuccess) return hip_fail(e_); \
+  } while (0)
+
+int run_modup(const ks_params* p, const ks_plan& plan, const uint64_t* d, uint64_t* ext, int batch, uint64_t* t1,
+              hipStream_t s) {
+  const ks::DevTables& tb = p->tb;
+  KS_TRY(traced(KS_K_INTT_D, s, [&] { return ks::launch_intt_blocks(tb, plan.log_r, d, t1, tb.ell, batch, s); }));
+  KS_TRY(traced(KS_K_MODUP_COLS, s, [&] { return ks::launch_modup_cols(tb, plan.log_r, t1, ext, 0, tb.ndig, tb.ndig, 1, 0, tb.nl, batch, s); }));
+  KS_TRY(traced(KS_K_EXT_BLOCKS, s, [&] { return ks::launch_ext_blocks(tb, plan.log_r, ext, batch, s); }));
+  KS_TRY(traced(KS_K_COPY_DIGITS, s, [&] { return ks::launch_copy_digits(tb, d, ext, batch, s); }));
+  return KS_OK;
+}
+
+int run_moddown(const ks_params* p, const ks_plan& plan, const uint64_t* acc, uint64_t* out, int batch,
+                uint64_t* accp, uint64_t* t2, hipStream_t s) {
+  const ks::DevTables& tb = p->tb;
+  KS_TRY(traced(KS_K_PBLOCKS_INV, s, [&] { return ks::launch_pblocks_inv(tb, plan.log_r, acc, accp, batch, s); }));
+  KS_TRY(traced(KS_K_MODDOWN_COLS, s, [&] { return ks::launch_moddown_cols(tb, plan.log_r, accp, t2, 0, tb.ell, batch, s); }));
+  KS_TRY(traced(KS_K_MODDOWN_BLOCKS, s, [&] { return ks::launch_moddown_blocks(tb, plan.log_r, t2, acc, out, 0, tb.ell, batch, s); }));
+  return KS_OK;
+}
+
+int run_fused(const ks_params* p, const ks_plan& plan, const uint64_t* d, const uint64_t* evk, uint64_t* out,
+              int batch, char* ws, hipStream_t s, int* launches) {
+  const ks::DevTables& tb = p->tb;
+  const Layout L = layout(p, batch, plan);
+  uint64_t* t1 = reinterpret_cast<uint64_t*>(ws + L.t1);
+  uint64_t* ext1 = reinterpret_cast<uint64_t*>(ws + L.ext1);
+  uint64_t* acc = reinterpret_cast<uint64_t*>(ws + L.acc);
+  uint64_t* t2 = reinterpret_cast<uint64_t*>(ws + L.t2);
+  const bool dp = plan.dataflow == KS_DPOB || plan.dataflow == KS_DPOC;
+  const int c = plan.chunks;
+  int count = 0;
+  const bool run = launches == nullptr;
+  if (run) KS_TRY(traced(KS_K_INTT_D, s, [&] { return ks::launch_intt_blocks(tb, plan.log_r, d, t1, tb.ell, batch, s); }));
+  ++count;
+  for (int ci = 0; ci < c; ++ci) {
+    int a, b;
+    chunk_range(tb.nl, c, ci, a, b);
+    if (a == b) continue;
+    if (dp) {
+      if (run) {
+        KS_TRY(traced(KS_K_MODUP_COLS, s, [&] { return ks::launch_modup_cols(tb, plan.log_r, t1, ext1, 0, tb.ndig, L.nslots, 1, a, b, batch, s); }));
+        KS_TRY(traced(KS_K_KEYMULT_BLOCKS, s, [&] { return ks::launch_keymult_blocks(tb, plan.log_r, d, ext1, evk, acc, 0, tb.ndig, L.nslots, 1, a, b, batch, 0,
+                                         1, s); }));
+      }
+      count += 2;
+    } else {
+      for (int j = 0; j < tb.ndig; ++j) {
+        if (run) {
+          KS_TRY(traced(KS_K_MODUP_COLS, s, [&] { return ks::launch_modup_cols(tb, plan.log_r, t1, ext1, j, 1, 1, 0, a, b, batch, s); }));
+          KS_TRY(traced(KS_K_KEYMULT_BLOCKS, s, [&] { return ks::launch_keymult_blocks(tb, plan.log_r, d, ext1, evk, acc, j, j + 1, 1, 0, a, b, batch, j > 0,
+                                           j == tb.ndig - 1, s); }));
+        }
+        count += 2;
+      }
+    }
+  }
+  for (int ci = 0; ci < c; ++ci) {
+    int a, b;
+    chunk_range(tb.ell, c, ci, a, b);
+    if (a == b) continue;
+    if (run) {
+      KS_TRY(traced(KS_K_MODDOWN_COLS, s, [&] { return ks::launch_moddown_cols(tb, plan.log_r, acc, t2, a, b, batch, s); }));
+      KS_TRY(traced(KS_K_MODDOWN_BLOCKS, s, [&] { return ks::launch_moddown_blocks(tb, plan.log_r, t2, acc, out, a, b, batch, s); }));
+    }
+    count += 2;
+  }
+  if (launches) *launches = count;
+  return KS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ks_params_create(int dnum, int log_n, int ell, ks_params** out) {
+  if (!out) return KS_ENULL;
+  *out = nullptr;
+  if (log_n < 3 || log_n > 17 || ell < 1 || dnum < 1 || dnum > ell) return KS_EINVAL;
+  const int alpha = (ell + dnum - 1) / dnum;
+  if (ell + alpha > KS_MAX_LIMBS) return KS_EINVAL;
+  ks_params* p = new (std::nothrow) ks_params;
+  if (!p) return KS_ENOMEM;
+  if (!ks::derive_params(dnum, log_n, ell, p->hp)) {
+    delete p;
+    return KS_EINVAL;
+  }
+  std::vector<uint64_t> blob;
+  ks::build_tables(p->hp, blob, p->tb);
+  hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) e = hipMalloc(&p->blob, blob.size() * sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMemcpy(p->blob, blob.data(), blob.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (p->blob) (void)hipFree(p->blob);
+    delete p;
+    return e == hipErrorOutOfMemory ? KS_ENOMEM : hip_fail(e);
+  }
+  const uintptr_t base = reinterpret_cast<uintptr_t>(p->blob);
+  auto rebase = [base](auto& ptr) {
+    ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(base + reinterpret_cast<uintptr_t>(ptr));
+  };
+  rebase(p->tb.limb);
+  rebase(p->tb.twf);
+  rebase(p->tb.twi);
+  rebase(p->tb.up_pre);
+  rebase(p->tb.up_mat);
+  rebase(p->tb.dn_pre);
+  rebase(p->tb.dn_mat);
+  rebase(p->tb.dn_pinv);
+  rebase(p->tb.up_hinv);
+  rebase(p->tb.dn_hinv);
+  *out = p;
+  return KS_OK;
+}
+
+void ks_params_destroy(ks_params* p) {
+  if (!p) return;
+  if (p->blob) (void)hipFree(p->blob);
+  delete p;
+}
+
+int ks_params_info(const ks_params* p, ks_info* info) {
+  if (!p || !info) return KS_ENULL;
+  std::memset(info, 0, sizeof(*info));
+  info->n = (int)p->hp.n;
+  info->log_n = p->hp.log_n;
+  info->ell = p->hp.ell;
+  info->k = p->hp.k;
+  info->alpha = p->hp.alpha;
+  info->dnum = p->hp.dnum;
+  info->ndig = p->hp.ndig;
+  for (int t = 0; t < p->hp.nl; ++t) {
+    info->moduli[t] = p->hp.mod[t];
+    info->psi[t] = p->hp.psi[t];
+  }
+  return KS_OK;
+}
+
+int ks_default_plan(const ks_params* p, int batch, ks_plan* plan) {
+  if (!p || !plan) return KS_ENULL;
+  if (batch < 0) return KS_EINVAL;
+  return resolve_plan(p, nullptr, *plan);
+}
+
+int ks_workspace_bytes(const ks_params* p, int batch, const ks_plan* plan, size_t* bytes) {
+  if (!p || !bytes) return KS_ENULL;
+  if (batch < 0) return KS_EINVAL;
+  ks_plan pl;
+  const int rc = resolve_plan(p, plan, pl);
+  if (rc != KS_OK) return rc;
+  *bytes = layout(p, batch, pl).total;
+  return KS_OK;
+}
+
+int ks_launch_count(const ks_params* p, int batch, const ks_plan* plan) {
+  if (!p) return KS_ENULL;
+  ks_plan pl;
+  const int rc = resolve_plan(p, plan, pl);
+  if (rc != KS_OK) return rc;
+  if (batch == 0) return 0;
+  if (pl.dataflow == KS_STAGED) return 4 + 1 + 3;
+  int n = 0;
+  run_fused(p, pl, nullptr, nullptr, nullptr, batch, nullptr, nullptr, &n);
+  return n;
+}
+
+static int check_limbs(const ks_params* p, int first, int n_limbs, int batch) {
+  if (first < 0 || n_limbs < 0 || first + n_limbs > p->hp.nl || batch < 0) return KS_EINVAL;
+  if ((long)n_limbs * batch > 65535L * 65535L) return KS_EINVAL;
+  return KS_OK;
+}
+
+int ks_ntt(const ks_params* p, uint64_t* x, int basis_first, int n_limbs, int batch, void* stream) {
+  if (!p) return KS_ENULL;
+  int rc = check_limbs(p, basis_first, n_limbs, batch);
+  if (rc != KS_OK) return rc;
+  if (n_limbs == 0 || batch == 0) return KS_OK;
+  if ((rc = check_ptr(x)) != KS_OK) return rc;
+  KS_TRY(traced(KS_K_NTT, (hipStream_t)stream, [&] { return ks::launch_ntt(p->tb, default_log_r(p->hp.log_n), x, basis_first, n_limbs, batch, (hipStream_t)stream); }));
+  return KS_OK;
+}
+
+int ks_intt(const ks_params* p, uint64_t* x, int basis_first, int n_limbs, int batch, void* stream) {
+  if (!p) return KS_ENULL;
+  int rc = check_limbs(p, basis_first, n_limbs, batch);
+  if (rc != KS_OK) return rc;
+  if (n_limbs == 0 || batch == 0) return KS_OK;
+  if ((rc = check_ptr(x)) != KS_OK) return rc;
+  KS_TRY(traced(KS_K_NTT, (hipStream_t)stream, [&] { return ks::launch_intt(p->tb, default_log_r(p->hp.log_n), x, basis_first, n_limbs, batch, (hipStream_t)stream); }));
+  return KS_OK;
+}
+
+int ks_bconv(const ks_params* p, const uint64_t* src, int src_set, uint64_t* dst, int batch, void* stream) {
+  if (!p) return KS_ENULL;
+  if (batch < 0 || batch > 65535) return KS_EINVAL;
+  if (src_set != KS_SET_P && (src_set < 0 || src_set >= p->hp.ndig)) return KS_EINVAL;
+  if (batch == 0) return KS_OK;
+  int rc;
+  if ((rc = check_ptr(src)) != KS_OK || (rc = check_ptr(dst)) != KS_OK) return rc;
+  KS_TRY(traced(KS_K_BCONV, (hipStream_t)stream, [&] { return ks::launch_bconv(p->tb, src, src_set, dst, batch, (hipStream_t)stream); }));
+  return KS_OK;
+}
+
+int ks_modup(const ks_params* p, const uint64_t* d, uint64_t* ext, int batch, void* ws, void* stream) {
+  if (!p) return KS_ENULL;
+  if (batch < 0 || batch * p->hp.ndig > 65535) return KS_EINVAL;
+  if (batch == 0) return KS_OK;
+  int rc;
+  if ((rc = check_ptr(d)) != KS_OK || (rc = check_ptr(ext)) != KS_OK || (rc = check_ptr(ws)) != KS_OK) return rc;
+  ks_plan pl;
+  const ks_plan staged{KS_STAGED, 1, 0, 0};
+  if ((rc = resolve_plan(p, &staged, pl)) != KS_OK) return rc;
+  return run_modup(p, pl, d, ext, batch, reinterpret_cast<uint64_t*>(ws), (hipStream_t)stream);
+}
+
+int ks_keymult(const ks_params* p, const uint64_t* ext, const uint64_t* evk, uint64_t* acc, int batch,
+               void* stream) {
+  if (!p) return KS_ENULL;
+  if (batch < 0 || batch > 65535) return KS_EINVAL;
+  if (batch == 0) return KS_OK;
+  int rc;
+  if ((rc = check_ptr(ext)) != KS_OK || (rc = check_ptr(evk)) != KS_OK || (rc = check_ptr(acc)) != KS_OK) return rc;
+  KS_TRY(traced(KS_K_KEYMULT, (hipStream_t)stream, [&] { return ks::launch_keymult(p->tb, ext, evk, acc, batch, (hipStream_t)stream); }));
+  return KS_OK;
+}
+
+int ks_moddown(const ks_params* p, const uint64_t* acc, uint64_t* out, int batch, void* ws, void* stream) {
+  if (!p) return KS_ENULL;
+  if (batch < 0 || batch * 2 > 65535) return KS_EINVAL;
+  if (batch == 0) return KS_OK;
+  int rc;
+  if ((rc = check_ptr(acc)) != KS_OK || (rc = check_ptr(out)) != KS_OK || (rc = check_ptr(ws)) != KS_OK) return rc;
+  ks_plan pl;
+  const ks_plan staged{KS_STAGED, 1, 0, 0};
+  if ((rc = resolve_plan(p, &staged, pl)) != KS_OK) return rc;
+  const size_t accp_bytes = up256((size_t)batch * 2 * p->hp.nl * p->hp.n * sizeof(uint64_t));
+  uint64_t* accp = reinterpret_cast<uint64_t*>(ws);
+  uint64_t* t2 = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(ws) + accp_bytes);
+  return run_moddown(p, pl, acc, out, batch, accp, t2, (hipStream_t)stream);
+}
+
+int ks_keyswitch(const ks_params* p, const uint64_t* d, const uint64_t* evk, uint64_t* out, int batch,
+                 const ks_plan* plan, void* ws, void* stream) {
+  if (!p) return KS_ENULL;
+  if (batch < 0 || batch * std::max(2, p->hp.ndig) > 65535) return KS_EINVAL;
+  ks_plan pl;
+  int rc = resolve_plan(p, plan, pl);
+  if (rc != KS_OK) return rc;
+  if (batch == 0) return KS_OK;
+  if ((rc = check_ptr(d)) != KS_OK || (rc = check_ptr(evk)) != KS_OK || (rc = check_ptr(out)) != KS_OK ||
+      (rc = check_ptr(ws)) != KS_OK)
+    return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (pl.dataflow == KS_STAGED) {
+    const Layout L = layout(p, batch, pl);
+    char* w = reinterpret_cast<char*>(ws);
+    uint64_t* ext = reinterpret_cast<uint64_t*>(w + L.ext);
+    uint64_t* acc = reinterpret_cast<uint64_t*>(w + L.acc);
+    if ((rc = run_modup(p, pl, d, ext, batch, reinterpret_cast<uint64_t*>(w + L.t1), s)) != KS_OK) return rc;
+    KS_TRY(traced(KS_K_KEYMULT, s, [&] { return ks::launch_keymult(p->tb, ext, evk, acc, batch, s); }));
+    return run_moddown(p, pl, acc, out, batch, reinterpret_cast<uint64_t*>(w + L.accp),
+                       reinterpret_cast<uint64_t*>(w + L.t2), s);
+  }
+  return run_fused(p, pl, d, evk, out, batch, reinterpret_cast<char*>(ws), s, nullptr);
+}
+
+const char* ks_strerror(int code) {
+  switch (code) {
+    case KS_OK: return "ok";
+    case KS_EINVAL: return "invalid argument";
+    case KS_ENULL: return "null pointer";
+    case KS_EALIGN: return "pointer not 256-byte aligned";
+    case KS_ENOMEM: return "out of memory";
+    case KS_EUNSUP: return "plan not supported for these parameters";
+    case KS_EHIP: return "HIP error";
+    default: return "unknown error";
+  }
+}
+
+const char* ks_last_hip_error(void) { return g_hip_error.c_str(); }
+
+int ks_trace_begin(void** events, int capacity, unsigned kind_mask) {
+  if (!events && capacity > 0) return KS_ENULL;
+  if (capacity < 0) return KS_EINVAL;
+  Trace& t = g_trace;
+  t.active = true;
+  t.events = reinterpret_cast<hipEvent_t*>(events);
+  t.cap = capacity;
+  t.n = 0;
+  t.mask = kind_mask;
+  t.kinds.clear();
+  return KS_OK;
+}
+
+int ks_trace_end(int* kinds, int capacity) {
+  Trace& t = g_trace;
+  if (!t.active) return 0;
+  const int n = t.n;
+  if (kinds)
+    for (int i = 0; i < n && i < capacity; ++i) kinds[i] = t.kinds[i];
+  t = Trace{};
+  return n;
+}
+
+}  // extern "C"

@@ -1,0 +1,235 @@
+// Host-side derivation of the parameters of one (dnum, N, ell) set and of
+// every constant table the kernels read.
+//
+// Parameter rules (the paper leaves them open): Q holds the ell largest
+// primes below 2^50 and P the k = alpha largest primes below 2^60, all
+// = 1 (mod 2N), in descending order; psi is the smallest primitive 2N-th root
+// of unity modulo each prime; alpha = ceil(ell / dnum).
+#include "ks_host.hpp"
+
+#include <algorithm>
+
+namespace ks {
+
+using u128 = unsigned __int128;
+
+uint64_t host_mulmod(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); }
+
+uint64_t host_powmod(uint64_t a, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m, x = a % m;
+  for (; e; e >>= 1) {
+    if (e & 1) r = host_mulmod(r, x, m);
+    x = host_mulmod(x, x, m);
+  }
+  return r;
+}
+
+namespace {
+
+uint64_t inv_prime(uint64_t a, uint64_t p) { return host_powmod(a, p - 2, p); }
+
+// Strong probable-prime test to every base in {2..37}; exact below 3.3e24.
+bool strong_prime(uint64_t n) {
+  if (n < 2) return false;
+  const uint64_t small[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+  for (uint64_t p : small)
+    if (n % p == 0) return n == p;
+  int s = __builtin_ctzll(n - 1);
+  uint64_t d = (n - 1) >> s;
+  for (uint64_t a : small) {
+    uint64_t x = host_powmod(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool witness = true;
+    for (int r = 1; r < s && witness; ++r) {
+      x = host_mulmod(x, x, n);
+      if (x == n - 1) witness = false;
+    }
+    if (witness) return false;
+  }
+  return true;
+}
+
+bool largest_primes(int bits, uint64_t step, int count, std::vector<uint64_t>& out) {
+  const uint64_t limit = (bits >= 64) ? ~0ull : ((1ull << bits) - 1);
+  uint64_t c = limit - (limit % step) + 1;  // largest value = 1 (mod step) not above limit + 1
+  if (c > limit) c -= step;
+  for (int got = 0; got < count; c -= step) {
+    if (c <= step) return false;
+    if (strong_prime(c)) {
+      out.push_back(c);
+      ++got;
+    }
+  }
+  return true;
+}
+
+uint64_t smallest_root(uint64_t q, uint64_t n) {
+  uint64_t g = 0;
+  for (uint64_t x = 2; x < q && !g; ++x) {
+    const uint64_t c = host_powmod(x, (q - 1) / (2 * n), q);
+    if (host_powmod(c, n, q) == q - 1) g = c;
+  }
+  const uint64_t g2 = host_mulmod(g, g, q);
+  uint64_t cur = g, best = g;
+  for (uint64_t e = 0; e < n; ++e) {
+    best = std::min(best, cur);
+    cur = host_mulmod(cur, g2, q);
+  }
+  return best;
+}
+
+uint32_t bitrev(uint32_t x, int bits) {
+  uint32_t r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1u) << (bits - 1 - i);
+  return r;
+}
+
+uint64_t shoup(uint64_t w, uint64_t q) { return (uint64_t)(((u128)w << 64) / q); }
+
+// -q^-1 mod 2^64 by Newton's iteration (q odd).
+uint64_t mont_neg_inv(uint64_t q) {
+  uint64_t x = q;  // correct to 3 bits
+  for (int i = 0; i < 6; ++i) x *= 2 - q * x;
+  return ~x + 1;
+}
+
+size_t align_words(size_t w) { return (w + 31) & ~(size_t)31; }
+
+}  // namespace
+
+bool derive_params(int dnum, int log_n, int ell, HostParams& hp) {
+  if (log_n < 3 || log_n > 17 || ell < 1 || dnum < 1 || dnum > ell) return false;
+  hp = HostParams{};
+  hp.dnum = dnum;
+  hp.log_n = log_n;
+  hp.ell = ell;
+  hp.n = (size_t)1 << log_n;
+  hp.alpha = (ell + dnum - 1) / dnum;
+  hp.k = hp.alpha;
+  hp.ndig = (ell + hp.alpha - 1) / hp.alpha;
+  hp.nl = ell + hp.k;
+  const uint64_t step = 2 * (uint64_t)hp.n;
+  if (!largest_primes(50, step, ell, hp.mod)) return false;
+  if (!largest_primes(60, step, hp.k, hp.mod)) return false;
+  for (uint64_t q : hp.mod) hp.psi.push_back(smallest_root(q, hp.n));
+  return true;
+}
+
+void build_tables(const HostParams& hp, std::vector<uint64_t>& blob, DevTables& tb) {
+  const size_t n = hp.n;
+  const int nl = hp.nl, ell = hp.ell, k = hp.k;
+  size_t off = 0;
+  auto take = [&](size_t words) {
+    const size_t o = off;
+    off = align_words(off + words);
+    return o;
+  };
+  const size_t o_limb = take((size_t)nl * (sizeof(LimbC) / 8));
+  const size_t o_twf = take((size_t)nl * n * 2);
+  const size_t o_twi = take((size_t)nl * n * 2);
+  const size_t o_up_pre = take((size_t)ell * 2);
+  const size_t o_up_mat = take((size_t)ell * nl * 2);
+  const size_t o_dn_pre = take((size_t)k * 2);
+  const size_t o_dn_mat = take((size_t)k * ell * 2);
+  const size_t o_dn_pinv = take((size_t)ell * 2);
+  const size_t o_up_hinv = take((size_t)ell * 2);
+  const size_t o_dn_hinv = take((size_t)k * 2);
+  blob.assign(off, 0);
+
+  auto put = [&](size_t o, uint64_t w, uint64_t q) {
+    blob[o] = w;
+    blob[o + 1] = shoup(w, q);
+  };
+
+  for (int t = 0; t < nl; ++t) {
+    const uint64_t q = hp.mod[t];
+    LimbC L{};
+    L.q = q;
+    L.two_q = 2 * q;
+    L.mont_ninv = mont_neg_inv(q);
+    const uint64_t r1 = (uint64_t)(((u128)1 << 64) % q);
+    L.r2 = host_mulmod(r1, r1, q);
+    L.ninv = inv_prime(n % q, q);
+    L.ninv_s = shoup(L.ninv, q);
+    L.red_s = shoup(1, q);
+    std::copy_n(reinterpret_cast<const uint64_t*>(&L), sizeof(LimbC) / 8, blob.begin() + o_limb + (size_t)t * 8);
+
+    // powers psi^e and psi^-e for e < N, then the bit-reversed tables
+    std::vector<uint64_t> pw(n), ipw(n);
+    const uint64_t psi = hp.psi[t], ipsi = inv_prime(psi, q);
+    pw[0] = ipw[0] = 1;
+    for (size_t e = 1; e < n; ++e) {
+      pw[e] = host_mulmod(pw[e - 1], psi, q);
+      ipw[e] = host_mulmod(ipw[e - 1], ipsi, q);
+    }
+    for (size_t i = 0; i < n; ++i) {
+      const uint32_t r = bitrev((uint32_t)i, hp.log_n);
+      put(o_twf + ((size_t)t * n + i) * 2, pw[r], q);
+      put(o_twi + ((size_t)t * n + i) * 2, ipw[r], q);
+    }
+  }
+
+  // ModUp: per source limb i of digit j
+  for (int i = 0; i < ell; ++i) {
+    const int j = i / hp.alpha;
+    const int lo = j * hp.alpha, hi = std::min(lo + hp.alpha, ell);
+    const uint64_t qi = hp.mod[i];
+    uint64_t hat = 1;
+    for (int i2 = lo; i2 < hi; ++i2)
+      if (i2 != i) hat = host_mulmod(hat, hp.mod[i2] % qi, qi);
+    const uint64_t hinv = inv_prime(hat, qi);
+    put(o_up_hinv + (size_t)i * 2, hinv, qi);
+    put(o_up_pre + (size_t)i * 2, host_mulmod(hinv, inv_prime(n % qi, qi), qi), qi);
+    for (int t = 0; t < nl; ++t) {
+      const uint64_t m = hp.mod[t];
+      uint64_t v = 1;
+      for (int i2 = lo; i2 < hi; ++i2)
+        if (i2 != i) v = host_mulmod(v, hp.mod[i2] % m, m);
+      put(o_up_mat + ((size_t)i * nl + t) * 2, v, m);
+    }
+  }
+
+  // ModDown
+  for (int m = 0; m < k; ++m) {
+    const uint64_t pm = hp.mod[ell + m];
+    uint64_t hat = 1;
+    for (int m2 = 0; m2 < k; ++m2)
+      if (m2 != m) hat = host_mulmod(hat, hp.mod[ell + m2] % pm, pm);
+    const uint64_t hinv = inv_prime(hat, pm);
+    put(o_dn_hinv + (size_t)m * 2, hinv, pm);
+    put(o_dn_pre + (size_t)m * 2, host_mulmod(hinv, inv_prime(n % pm, pm), pm), pm);
+    for (int i = 0; i < ell; ++i) {
+      const uint64_t qi = hp.mod[i];
+      uint64_t v = 1;
+      for (int m2 = 0; m2 < k; ++m2)
+        if (m2 != m) v = host_mulmod(v, hp.mod[ell + m2] % qi, qi);
+      put(o_dn_mat + ((size_t)m * ell + i) * 2, v, qi);
+    }
+  }
+  for (int i = 0; i < ell; ++i) {
+    const uint64_t qi = hp.mod[i];
+    uint64_t pmod = 1;
+    for (int m = 0; m < k; ++m) pmod = host_mulmod(pmod, hp.mod[ell + m] % qi, qi);
+    put(o_dn_pinv + (size_t)i * 2, inv_prime(pmod, qi), qi);
+  }
+
+  tb.log_n = hp.log_n;
+  tb.ell = ell;
+  tb.k = k;
+  tb.nl = nl;
+  tb.alpha = hp.alpha;
+  tb.ndig = hp.ndig;
+  auto at = [](size_t o) { return reinterpret_cast<const uint64_t*>(o * sizeof(uint64_t)); };
+  tb.limb = reinterpret_cast<const LimbC*>(at(o_limb));
+  tb.twf = at(o_twf);
+  tb.twi = at(o_twi);
+  tb.up_pre = at(o_up_pre);
+  tb.up_mat = at(o_up_mat);
+  tb.dn_pre = at(o_dn_pre);
+  tb.dn_mat = at(o_dn_mat);
+  tb.dn_pinv = at(o_dn_pinv);
+  tb.up_hinv = at(o_up_hinv);
+  tb.dn_hinv = at(o_dn_hinv);
+}
+
+}  // namespace ks

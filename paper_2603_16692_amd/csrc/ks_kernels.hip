@@ -1,0 +1,659 @@
+// HIP kernels of the KeySwitch path for gfx950, and their host launchers.
+//
+// A limb of N = R * M coefficients is transformed in two passes:
+//   * a column pass: thread c owns the R coefficients c, c + M, ..., and runs
+//     the first log R stages of the forward transform (or the last log R of the
+//     inverse) in registers; consecutive threads touch consecutive addresses;
+//   * a block pass: a workgroup owns M consecutive coefficients and runs the
+//     remaining log M stages through LDS (BlockNtt).
+// ModUp's BConv sits between the inverse column pass and the forward column
+// pass of the new limbs (same columns), KeyMult sits after the forward block
+// pass, and ModDown repeats the pattern. Every kernel keeps the element ranges
+// stated next to it; canonical residues leave the library.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ks_device.hpp"
+#include "ks_kernels.hpp"
+
+namespace ks {
+
+namespace {
+
+constexpr int TC = 64;  // threads of a column-pass workgroup
+
+__device__ __forceinline__ size_t lane_col(int M) { return (size_t)blockIdx.x * TC + threadIdx.x; }
+
+// ------------------------------------------------------- standalone passes
+
+// Column pass of ks_ntt / ks_intt on x [items][nlimbs][N] (limb r uses prime
+// first + r). Forward: [0, q) or [0, 4q) in -> [0, 4q) out. Inverse: [0, 2q) in
+// -> canonical out (includes N^-1).
+template <int LOGR, bool INV>
+__global__ __launch_bounds__(TC) void k_cols(DevTables tb, uint64_t* x, int first, int nlimbs, int log_m) {
+  constexpr int R = 1 << LOGR;
+  const int M = 1 << log_m;
+  const size_t c = lane_col(M);
+  if (c >= (size_t)M) return;
+  const int limb = first + blockIdx.y;
+  const LimbC L = tb.limb[limb];
+  const size_t N = (size_t)M * R;
+  uint64_t* a = x + ((size_t)blockIdx.z * nlimbs + blockIdx.y) * N;
+  uint64_t v[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) v[i] = a[c + (size_t)i * M];
+  if (!INV) {
+    sub_fwd<LOGR>(v, tb.twf + (size_t)limb * N * 2, 1u, L.q, L.two_q);
+  } else {
+    sub_inv<LOGR>(v, tb.twi + (size_t)limb * N * 2, 1u, L.q, L.two_q);
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = reduce2(mul_shoup(v[i], L.ninv, L.ninv_s, L.q), L.q);
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) a[c + (size_t)i * M] = v[i];
+}
+
+// Block pass of ks_ntt / ks_intt: block b of limb (blockIdx.y) of item
+// (blockIdx.z). Forward leaves canonical values; inverse takes canonical
+// values and leaves [0, 2q) (the column pass follows), or canonical values
+// times N^-1 when `scale` is set (a one-pass ks_intt).
+template <int LOGM, int LOGE, bool INV>
+__global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_blocks(DevTables tb, const uint64_t* src, uint64_t* dst,
+                                                                    int first, int nlimbs, int scale) {
+  using B = BlockNtt<LOGM, LOGE>;
+  extern __shared__ uint64_t lds[];
+  const int tid = threadIdx.x, b = blockIdx.x;
+  const int limb = first + blockIdx.y;
+  const LimbC L = tb.limb[limb];
+  const size_t N = (size_t)1 << tb.log_n;
+  const int R = (int)(N >> LOGM);
+  const size_t off = ((size_t)blockIdx.z * nlimbs + blockIdx.y) * N + (size_t)b * B::M;
+  const uint64_t* s = src + off;
+  uint64_t* d = dst + off;
+  uint64_t v[B::E];
+  if (!INV) {
+#pragma unroll
+    for (int i = 0; i < B::E; ++i) v[i] = s[B::fr_pos(tid, i)];
+    B::fwd(v, lds, tid, (uint32_t)(R + b), tb.twf + (size_t)limb * N * 2, L.q, L.two_q);
+#pragma unroll
+    for (int i = 0; i < B::E; ++i) d[B::lr_pos(tid, i)] = reduce4(v[i], L.q, L.two_q);
+  } else {
+#pragma unroll
+    for (int i = 0; i < B::E; ++i) v[i] = s[B::lr_pos(tid, i)];
+    B::inv(v, lds, tid, (uint32_t)(R + b), tb.twi + (size_t)limb * N * 2, L.q, L.two_q);
+    if (scale) {  // the whole transform was this block: apply N^-1 here
+#pragma unroll
+      for (int i = 0; i < B::E; ++i) v[i] = reduce2(mul_shoup(v[i], L.ninv, L.ninv_s, L.q), L.q);
+    }
+#pragma unroll
+    for (int i = 0; i < B::E; ++i) d[B::fr_pos(tid, i)] = v[i];
+  }
+}
+
+// ------------------------------------------------------------ ModUp (K2)
+
+// For digits j0 + blockIdx.y and columns c: INTT column pass of the digit's
+// limbs of t1 (block-pass output of d, [0, 2q)), times N^-1 [(D_j/q_i)^-1]
+// (canonical y_i, staged in LDS), BConv to every target limb t in
+// [tgt0, tgt1) outside D_j, forward column pass, store to ext1 slot.
+// ext1 [items][slots][nl][N]; slot = (slot_stride ? j : 0).
+template <int LOGR>
+__global__ __launch_bounds__(TC) void k_modup_cols(DevTables tb, const uint64_t* t1, uint64_t* ext1, int j0,
+                                                   int nslots, int slot_stride, int tgt0, int tgt1, int log_m) {
+  constexpr int R = 1 << LOGR;
+  extern __shared__ uint64_t ylds[];  // [alpha][R][TC]
+  const int M = 1 << log_m;
+  const size_t N = (size_t)M * R;
+  const size_t c = lane_col(M);
+  const bool live = c < (size_t)M;
+  const int j = j0 + blockIdx.y;
+  const int item = blockIdx.z;
+  const int lo = j * tb.alpha;
+  const int hi = min(lo + tb.alpha, tb.ell);
+  const int tid = threadIdx.x;
+  if (live) {
+    for (int i = lo; i < hi; ++i) {
+      const LimbC L = tb.limb[i];
+      const uint64_t* a = t1 + ((size_t)item * tb.ell + i) * N;
+      uint64_t v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = a[c + (size_t)r * M];
+      sub_inv<LOGR>(v, tb.twi + (size_t)i * N * 2, 1u, L.q, L.two_q);
+      const uint64_t w = tb.up_pre[2 * i], ws = tb.up_pre[2 * i + 1];
+#pragma unroll
+      for (int r = 0; r < R; ++r) ylds[((i - lo) * R + r) * TC + tid] = reduce2(mul_shoup(v[r], w, ws, L.q), L.q);
+    }
+  }
+  if (!live) return;
+  const int slot = slot_stride ? j : 0;
+  uint64_t* e = ext1 + ((size_t)item * nslots + slot) * (size_t)tb.nl * N;
+  for (int t = tgt0; t < tgt1; ++t) {
+    if (t >= lo && t < hi) continue;
+    const LimbC L = tb.limb[t];
+    uint64_t z[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) z[r] = 0;
+    for (int i = lo; i < hi; ++i) {
+      const uint64_t w = tb.up_mat[2 * ((size_t)i * tb.nl + t)], ws = tb.up_mat[2 * ((size_t)i * tb.nl + t) + 1];
+#pragma unroll
+      for (int r = 0; r < R; ++r) z[r] += reduce2(mul_shoup(ylds[((i - lo) * R + r) * TC + tid], w, ws, L.q), L.q);
+      if (((i - lo) & 7) == 7) {  // keep the sum below 8q < 2^63
+#pragma unroll
+        for (int r = 0; r < R; ++r) z[r] = reduce2(mul_shoup(z[r], 1, L.red_s, L.q), L.q);
+      }
+    }
+    // the sum holds at most 8 values below q: fold with Shoup by 1
+#pragma unroll
+    for (int r = 0; r < R; ++r) z[r] = reduce2(mul_shoup(z[r], 1, L.red_s, L.q), L.q);
+    sub_fwd<LOGR>(z, tb.twf + (size_t)t * N * 2, 1u, L.q, L.two_q);
+    uint64_t* o = e + (size_t)t * N;
+#pragma unroll
+    for (int r = 0; r < R; ++r) o[c + (size_t)r * M] = z[r];
+  }
+}
+
+// ---------------------------------------------------------- KeyMult (K3)
+
+// Block b of target limb t = tgt0 + blockIdx.y of item blockIdx.z: for every
+// digit j in [j0, j1): ext_j = (t in D_j) ? d : forward block pass of ext1;
+// s_c += ext_j * evk[j][c] (Montgomery). Then v_c = s_c * R^2 (canonical),
+// plus the previous acc if `accumulate`. With `finalize` and t a P limb, the
+// inverse block pass of ModDown runs on v_c (result in [0, 2q), FR layout);
+// otherwise v_c is stored canonical (LR layout).
+template <int LOGM, int LOGE>
+__global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_keymult_blocks(
+    DevTables tb, const uint64_t* d, const uint64_t* ext1, const uint64_t* evk, uint64_t* acc, int j0, int j1,
+    int nslots, int slot_stride, int tgt0, int accumulate, int finalize) {
+  using B = BlockNtt<LOGM, LOGE>;
+  extern __shared__ uint64_t lds[];
+  const int tid = threadIdx.x, b = blockIdx.x;
+  const int t = tgt0 + blockIdx.y;
+  const int item = blockIdx.z;
+  const LimbC L = tb.limb[t];
+  const size_t N = (size_t)1 << tb.log_n;
+  const int R = (int)(N >> LOGM);
+  const int nl = tb.nl;
+  const size_t boff = (size_t)b * B::M;
+  uint64_t s0[B::E], s1[B::E], v[B::E];
+#pragma unroll
+  for (int i = 0; i < B::E; ++i) s0[i] = s1[i] = 0;
+  for (int j = j0; j < j1; ++j) {
+    const int lo = j * tb.alpha, hi = min(lo + tb.alpha, tb.ell);
+    if (t >= lo && t < hi) {
+      const uint64_t* src = d + ((size_t)item * tb.ell + t) * N + boff;
+#pragma unroll
+      for (int i = 0; i < B::E; ++i) v[i] = src[B::lr_pos(tid, i)];
+    } else {
+      const int slot = slot_stride ? j : 0;
+      const uint64_t* src = ext1 + (((size_t)item * nslots + slot) * nl + t) * N + boff;
+#pragma unroll
+      for (int i = 0; i < B::E; ++i) v[i] = src[B::fr_pos(tid, i)];
+      B::fwd(v, lds, tid, (uint32_t)(R + b), tb.twf + (size_t)t * N * 2, L.q, L.two_q);
+    }
+    const uint64_t* k0 = evk + (((size_t)j * 2 + 0) * nl + t) * N + boff;
+    const uint64_t* k1 = evk + (((size_t)j * 2 + 1) * nl + t) * N + boff;
+#pragma unroll
+    for (int i = 0; i < B::E; ++i) {
+      const int x = B::lr_pos(tid, i);
+      // running sums stay in [0, 2q): each product is in [0, 2q)
+      s0[i] += mont_mul(v[i], k0[x], L.q, L.mont_ninv);
+      s0[i] = s0[i] >= L.two_q ? s0[i] - L.two_q : s0[i];
+      s1[i] += mont_mul(v[i], k1[x], L.q, L.mont_ninv);
+      s1[i] = s1[i] >= L.two_q ? s1[i] - L.two_q : s1[i];
+    }
+  }
+  uint64_t* a0 = acc + (((size_t)item * 2 + 0) * nl + t) * N + boff;
+  uint64_t* a1 = acc + (((size_t)item * 2 + 1) * nl + t) * N + boff;
+#pragma unroll
+  for (int i = 0; i < B::E; ++i) {
+    // s < 2q, so s * r2 < 2 q^2 < q * 2^64
+    s0[i] = reduce2(mont_mul(s0[i], L.r2, L.q, L.mont_ninv), L.q);
+    s1[i] = reduce2(mont_mul(s1[i], L.r2, L.q, L.mont_ninv), L.q);
+  }
+  if (accumulate) {
+#pragma unroll
+    for (int i = 0; i < B::E; ++i) {
+      const int x = B::lr_pos(tid, i);
+      s0[i] = reduce2(s0[i] + a0[x], L.q);
+      s1[i] = reduce2(s1[i] + a1[x], L.q);
+    }
+  }
+  if (finalize && t >= tb.ell) {
+    const uint64_t* twi = tb.twi + (size_t)t * N * 2;
+    B::inv(s0, lds, tid, (uint32_t)(R + b), twi, L.q, L.two_q);
+#pragma unroll
+    for (int i = 0; i < B::E; ++i) a0[B::fr_pos(tid, i)] = s0[i];
+    B::inv(s1, lds, tid, (uint32_t)(R + b), twi, L.q, L.two_q);
+#pragma unroll
+    for (int i = 0; i < B::E; ++i) a1[B::fr_pos(tid, i)] = s1[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < B::E; ++i) {
+      const int x = B::lr_pos(tid, i);
+      a0[x] = s0[i];
+      a1[x] = s1[i];
+    }
+  }
+}
+
+// ---------------------------------------------------------- ModDown (K4)
+
+// Columns of component blockIdx.y of item blockIdx.z: INTT column pass of
+// the k P limbs (inputs: the block-pass output, [0, 2q), read from accp
+// [items][2][nl][N] at limbs ell..nl-1), times N^-1 [(P/p_m)^-1] (canonical y_m
+// in LDS), BConv to Q limbs i in [tgt0, tgt1), forward column pass, store to
+// t2 [items][2][ell][N].
+template <int LOGR>
+__global__ __launch_bounds__(TC) void k_moddown_cols(DevTables tb, const uint64_t* accp, uint64_t* t2, int tgt0,
+                                                     int tgt1, int log_m) {
+  constexpr int R = 1 << LOGR;
+  extern __shared__ uint64_t ylds[];  // [k][R][TC]
+  const int M = 1 << log_m;
+  const size_t N = (size_t)M * R;
+  const size_t c = lane_col(M);
+  if (c >= (size_t)M) return;
+  const int comp = blockIdx.y, item = blockIdx.z, tid = threadIdx.x;
+  const int ell = tb.ell, nl = tb.nl;
+  for (int m = 0; m < tb.k; ++m) {
+    const LimbC L = tb.limb[ell + m];
+    const uint64_t* a = accp + (((size_t)item * 2 + comp) * nl + ell + m) * N;
+    uint64_t v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = a[c + (size_t)r * M];
+    sub_inv<LOGR>(v, tb.twi + (size_t)(ell + m) * N * 2, 1u, L.q, L.two_q);
+    const uint64_t w = tb.dn_pre[2 * m], ws = tb.dn_pre[2 * m + 1];
+#pragma unroll
+    for (int r = 0; r < R; ++r) ylds[(m * R + r) * TC + tid] = reduce2(mul_shoup(v[r], w, ws, L.q), L.q);
+  }
+  for (int i = tgt0; i < tgt1; ++i) {
+    const LimbC L = tb.limb[i];
+    uint64_t z[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) z[r] = 0;
+    for (int m = 0; m < tb.k; ++m) {
+      const uint64_t w = tb.dn_mat[2 * ((size_t)m * ell + i)], ws = tb.dn_mat[2 * ((size_t)m * ell + i) + 1];
+#pragma unroll
+      for (int r = 0; r < R; ++r) z[r] += reduce2(mul_shoup(ylds[(m * R + r) * TC + tid], w, ws, L.q), L.q);
+      if ((m & 7) == 7) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) z[r] = reduce2(mul_shoup(z[r], 1, L.red_s, L.q), L.q);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) z[r] = reduce2(mul_shoup(z[r], 1, L.red_s, L.q), L.q);
+    sub_fwd<LOGR>(z, tb.twf + (size_t)i * N * 2, 1u, L.q, L.two_q);
+    uint64_t* o = t2 + (((size_t)item * 2 + comp) * ell + i) * N;
+#pragma unroll
+    for (int r = 0; r < R; ++r) o[c + (size_t)r * M] = z[r];
+  }
+}
+
+// ---------------------------------------------------------- ModDown (K5)
+
+// Block b of Q limb i = tgt0 + blockIdx.y, component/item blockIdx.z = item*2+c:
+// forward block pass of t2, then out = (acc_Q - v) * P^-1 (canonical).
+template <int LOGM, int LOGE>
+__global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_moddown_blocks(DevTables tb, const uint64_t* t2,
+                                                                            const uint64_t* acc, uint64_t* out,
+                                                                            int tgt0) {
+  using B = BlockNtt<LOGM, LOGE>;
+  extern __shared__ uint64_t lds[];
+  const int tid = threadIdx.x, b = blockIdx.x;
+  const int i = tgt0 + blockIdx.y;
+  const int ic = blockIdx.z;  // item * 2 + component
+  const LimbC L = tb.limb[i];
+  const size_t N = (size_t)1 << tb.log_n;
+  const int R = (int)(N >> LOGM);
+  const size_t boff = (size_t)b * B::M;
+  const uint64_t* src = t2 + ((size_t)ic * tb.ell + i) * N + boff;
+  uint64_t v[B::E];
+#pragma unroll
+  for (int e = 0; e < B::E; ++e) v[e] = src[B::fr_pos(tid, e)];
+  B::fwd(v, lds, tid, (uint32_t)(R + b), tb.twf + (size_t)i * N * 2, L.q, L.two_q);
+  const uint64_t* a = acc + ((size_t)ic * tb.nl + i) * N + boff;
+  uint64_t* o = out + ((size_t)ic * tb.ell + i) * N + boff;
+  const uint64_t w = tb.dn_pinv[2 * i], ws = tb.dn_pinv[2 * i + 1];
+  const uint64_t four_q = 2 * L.two_q;
+#pragma unroll
+  for (int e = 0; e < B::E; ++e) {
+    const int x = B::lr_pos(tid, e);
+    o[x] = reduce2(mul_shoup(a[x] + four_q - v[e], w, ws, L.q), L.q);
+  }
+}
+
+// ------------------------------------------------------ standalone kernels
+
+// ks_modup: forward block pass of every non-digit limb of ext (in place).
+template <int LOGM, int LOGE>
+__global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_ext_blocks(DevTables tb, uint64_t* ext) {
+  using B = BlockNtt<LOGM, LOGE>;
+  extern __shared__ uint64_t lds[];
+  const int tid = threadIdx.x, b = blockIdx.x;
+  const int t = blockIdx.y;
+  const int j = blockIdx.z % tb.ndig;
+  const int lo = j * tb.alpha, hi = min(lo + tb.alpha, tb.ell);
+  if (t >= lo && t < hi) return;  // uniform over the workgroup
+  const LimbC L = tb.limb[t];
+  const size_t N = (size_t)1 << tb.log_n;
+  const int R = (int)(N >> LOGM);
+  uint64_t* a = ext + ((size_t)blockIdx.z * tb.nl + t) * N + (size_t)b * B::M;
+  uint64_t v[B::E];
+#pragma unroll
+  for (int e = 0; e < B::E; ++e) v[e] = a[B::fr_pos(tid, e)];
+  B::fwd(v, lds, tid, (uint32_t)(R + b), tb.twf + (size_t)t * N * 2, L.q, L.two_q);
+#pragma unroll
+  for (int e = 0; e < B::E; ++e) a[B::lr_pos(tid, e)] = reduce4(v[e], L.q, L.two_q);
+}
+
+// ext[item][j][t] = d[item][t] for t in D_j.
+__global__ void k_copy_digits(DevTables tb, const uint64_t* d, uint64_t* ext) {
+  const size_t N = (size_t)1 << tb.log_n;
+  const size_t x = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= N) return;
+  const int t = blockIdx.y, item = blockIdx.z;
+  const int j = t / tb.alpha;
+  ext[(((size_t)item * tb.ndig + j) * tb.nl + t) * N + x] = d[((size_t)item * tb.ell + t) * N + x];
+}
+
+// ks_bconv: coefficient-form conversion of one source set, one thread per
+// coefficient. src [items][ns][N], dst [items][nd][N].
+__global__ void k_bconv(DevTables tb, const uint64_t* src, uint64_t* dst, int set) {
+  const size_t N = (size_t)1 << tb.log_n;
+  const size_t x = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= N) return;
+  const int u = blockIdx.y, item = blockIdx.z;
+  int lo, hi, t;
+  if (set < 0) {
+    lo = tb.ell;
+    hi = tb.nl;
+    t = u;
+  } else {
+    lo = set * tb.alpha;
+    hi = min(lo + tb.alpha, tb.ell);
+    t = u < lo ? u : u + (hi - lo);
+  }
+  const int ns = hi - lo;
+  const int nd = tb.nl - ns;
+  const LimbC L = tb.limb[t];
+  uint64_t z = 0;
+  for (int s = 0; s < ns; ++s) {
+    const int i = lo + s;
+    const LimbC S = tb.limb[i];
+    // y_i = x_i * [(S/s_i)^-1]_{s_i}, canonical
+    const uint64_t* hinv = set < 0 ? tb.dn_hinv + 2 * s : tb.up_hinv + 2 * i;
+    const uint64_t xi = src[((size_t)item * ns + s) * N + x];
+    const uint64_t y = reduce2(mul_shoup(xi, hinv[0], hinv[1], S.q), S.q);
+    uint64_t cw, cws;
+    if (set < 0) {
+      cw = tb.dn_mat[2 * ((size_t)s * tb.ell + t)];
+      cws = tb.dn_mat[2 * ((size_t)s * tb.ell + t) + 1];
+    } else {
+      cw = tb.up_mat[2 * ((size_t)i * tb.nl + t)];
+      cws = tb.up_mat[2 * ((size_t)i * tb.nl + t) + 1];
+    }
+    z += reduce2(mul_shoup(y, cw, cws, L.q), L.q);
+    if ((s & 7) == 7) z = reduce2(mul_shoup(z, 1, L.red_s, L.q), L.q);
+  }
+  dst[((size_t)item * nd + u) * N + x] = reduce2(mul_shoup(z, 1, L.red_s, L.q), L.q);
+}
+
+// ks_keymult: element-wise over acc [items][2][nl][N].
+__global__ void k_keymult(DevTables tb, const uint64_t* ext, const uint64_t* evk, uint64_t* acc) {
+  const size_t N = (size_t)1 << tb.log_n;
+  const size_t x = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= N) return;
+  const int t = blockIdx.y % tb.nl, c = blockIdx.y / tb.nl, item = blockIdx.z;
+  const LimbC L = tb.limb[t];
+  uint64_t s = 0;
+  for (int j = 0; j < tb.ndig; ++j) {
+    s += mont_mul(ext[(((size_t)item * tb.ndig + j) * tb.nl + t) * N + x], evk[(((size_t)j * 2 + c) * tb.nl + t) * N + x],
+                  L.q, L.mont_ninv);
+    s = s >= L.two_q ? s - L.two_q : s;
+  }
+  acc[(((size_t)item * 2 + c) * tb.nl + t) * N + x] = reduce2(mont_mul(s, L.r2, L.q, L.mont_ninv), L.q);
+}
+
+// ks_moddown, first step: copy the P limbs of acc into the work buffer and
+// run the inverse block pass there (the caller's acc stays untouched).
+template <int LOGM, int LOGE>
+__global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_pblocks_inv(DevTables tb, const uint64_t* acc,
+                                                                         uint64_t* accp) {
+  using B = BlockNtt<LOGM, LOGE>;
+  extern __shared__ uint64_t lds[];
+  const int tid = threadIdx.x, b = blockIdx.x;
+  const int t = tb.ell + blockIdx.y;
+  const int ic = blockIdx.z;
+  const LimbC L = tb.limb[t];
+  const size_t N = (size_t)1 << tb.log_n;
+  const int R = (int)(N >> LOGM);
+  const size_t off = ((size_t)ic * tb.nl + t) * N + (size_t)b * B::M;
+  uint64_t v[B::E];
+#pragma unroll
+  for (int e = 0; e < B::E; ++e) v[e] = acc[off + B::lr_pos(tid, e)];
+  B::inv(v, lds, tid, (uint32_t)(R + b), tb.twi + (size_t)t * N * 2, L.q, L.two_q);
+#pragma unroll
+  for (int e = 0; e < B::E; ++e) accp[off + B::fr_pos(tid, e)] = v[e];
+}
+
+// ------------------------------------------------------------ dispatching
+
+template <template <int> class F, typename... A>
+hipError_t by_logr(int log_r, A... a) {
+  switch (log_r) {
+    case 0: return F<0>::run(a...);
+    case 1: return F<1>::run(a...);
+    case 2: return F<2>::run(a...);
+    case 3: return F<3>::run(a...);
+    case 4: return F<4>::run(a...);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+constexpr int loge_for(int logm) { return logm >= 8 ? 4 : (logm >= 4 ? 2 : 1); }
+
+template <template <int, int> class F, typename... A>
+hipError_t by_logm(int log_m, A... a) {
+  switch (log_m) {
+#define KS_CASE(m) \
+  case m: return F<m, loge_for(m)>::run(a...);
+    KS_CASE(3) KS_CASE(4) KS_CASE(5) KS_CASE(6) KS_CASE(7) KS_CASE(8) KS_CASE(9) KS_CASE(10) KS_CASE(11)
+    KS_CASE(12) KS_CASE(13) KS_CASE(14)
+#undef KS_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+dim3 col_grid(int log_m, int y, int z) { return dim3((unsigned)(((1 << log_m) + TC - 1) / TC), (unsigned)y, (unsigned)z); }
+
+template <int LOGM, int LOGE>
+size_t block_lds() {
+  return sizeof(uint64_t) * BlockNtt<LOGM, LOGE>::LDS_WORDS;
+}
+
+// Allows a kernel to take up to the whole 160 KB of LDS as dynamic shared
+// memory (done once per kernel instantiation).
+template <auto Kernel>
+void allow_lds() {
+  static const hipError_t once = hipFuncSetAttribute(reinterpret_cast<const void*>(Kernel),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  (void)once;
+}
+
+template <int LOGR>
+struct ColsFwd {
+  static hipError_t run(const DevTables& tb, uint64_t* x, int first, int nl, int items, int log_m, hipStream_t s) {
+    k_cols<LOGR, false><<<col_grid(log_m, nl, items), dim3(TC), 0, s>>>(tb, x, first, nl, log_m);
+    return hipGetLastError();
+  }
+};
+template <int LOGR>
+struct ColsInv {
+  static hipError_t run(const DevTables& tb, uint64_t* x, int first, int nl, int items, int log_m, hipStream_t s) {
+    k_cols<LOGR, true><<<col_grid(log_m, nl, items), dim3(TC), 0, s>>>(tb, x, first, nl, log_m);
+    return hipGetLastError();
+  }
+};
+template <int LOGM, int LOGE>
+struct BlocksFwd {
+  static hipError_t run(const DevTables& tb, const uint64_t* src, uint64_t* dst, int first, int nl, int items,
+                        int scale, hipStream_t s) {
+    using B = BlockNtt<LOGM, LOGE>;
+    allow_lds<k_blocks<LOGM, LOGE, false>>();
+    k_blocks<LOGM, LOGE, false><<<dim3(1u << (tb.log_n - LOGM), nl, items), dim3(B::T), block_lds<LOGM, LOGE>(), s>>>(tb, src, dst, first, nl, scale);
+    return hipGetLastError();
+  }
+};
+template <int LOGM, int LOGE>
+struct BlocksInv {
+  static hipError_t run(const DevTables& tb, const uint64_t* src, uint64_t* dst, int first, int nl, int items,
+                        int scale, hipStream_t s) {
+    using B = BlockNtt<LOGM, LOGE>;
+    allow_lds<k_blocks<LOGM, LOGE, true>>();
+    k_blocks<LOGM, LOGE, true><<<dim3(1u << (tb.log_n - LOGM), nl, items), dim3(B::T), block_lds<LOGM, LOGE>(), s>>>(tb, src, dst, first, nl, scale);
+    return hipGetLastError();
+  }
+};
+template <int LOGR>
+struct ModupCols {
+  static hipError_t run(const DevTables& tb, const uint64_t* t1, uint64_t* ext1, int j0, int nj, int nslots,
+                        int slot_stride, int tgt0, int tgt1, int items, int log_m, hipStream_t s) {
+    const size_t lds = sizeof(uint64_t) * (size_t)tb.alpha * (1 << LOGR) * TC;
+    allow_lds<k_modup_cols<LOGR>>();
+    k_modup_cols<LOGR><<<col_grid(log_m, nj, items), dim3(TC), lds, s>>>(tb, t1, ext1, j0, nslots, slot_stride, tgt0, tgt1, log_m);
+    return hipGetLastError();
+  }
+};
+template <int LOGM, int LOGE>
+struct KeymultBlocks {
+  static hipError_t run(const DevTables& tb, const uint64_t* d, const uint64_t* ext1, const uint64_t* evk,
+                        uint64_t* acc, int j0, int j1, int nslots, int slot_stride, int tgt0, int tgt1, int items,
+                        int accumulate, int finalize, hipStream_t s) {
+    using B = BlockNtt<LOGM, LOGE>;
+    allow_lds<k_keymult_blocks<LOGM, LOGE>>();
+    k_keymult_blocks<LOGM, LOGE><<<dim3(1u << (tb.log_n - LOGM), tgt1 - tgt0, items), dim3(B::T), block_lds<LOGM, LOGE>(), s>>>(tb, d, ext1, evk, acc, j0, j1, nslots, slot_stride, tgt0, accumulate, finalize);
+    return hipGetLastError();
+  }
+};
+template <int LOGR>
+struct ModdownCols {
+  static hipError_t run(const DevTables& tb, const uint64_t* accp, uint64_t* t2, int tgt0, int tgt1, int items,
+                        int log_m, hipStream_t s) {
+    const size_t lds = sizeof(uint64_t) * (size_t)tb.k * (1 << LOGR) * TC;
+    allow_lds<k_moddown_cols<LOGR>>();
+    k_moddown_cols<LOGR><<<col_grid(log_m, 2, items), dim3(TC), lds, s>>>(tb, accp, t2, tgt0, tgt1, log_m);
+    return hipGetLastError();
+  }
+};
+template <int LOGM, int LOGE>
+struct ModdownBlocks {
+  static hipError_t run(const DevTables& tb, const uint64_t* t2, const uint64_t* acc, uint64_t* out, int tgt0,
+                        int tgt1, int items, hipStream_t s) {
+    using B = BlockNtt<LOGM, LOGE>;
+    allow_lds<k_moddown_blocks<LOGM, LOGE>>();
+    k_moddown_blocks<LOGM, LOGE><<<dim3(1u << (tb.log_n - LOGM), tgt1 - tgt0, items * 2), dim3(B::T), block_lds<LOGM, LOGE>(), s>>>(tb, t2, acc, out, tgt0);
+    return hipGetLastError();
+  }
+};
+template <int LOGM, int LOGE>
+struct ExtBlocks {
+  static hipError_t run(const DevTables& tb, uint64_t* ext, int items, hipStream_t s) {
+    using B = BlockNtt<LOGM, LOGE>;
+    allow_lds<k_ext_blocks<LOGM, LOGE>>();
+    k_ext_blocks<LOGM, LOGE><<<dim3(1u << (tb.log_n - LOGM), tb.nl, items * tb.ndig), dim3(B::T), block_lds<LOGM, LOGE>(), s>>>(tb, ext);
+    return hipGetLastError();
+  }
+};
+template <int LOGM, int LOGE>
+struct PBlocksInv {
+  static hipError_t run(const DevTables& tb, const uint64_t* acc, uint64_t* accp, int items, hipStream_t s) {
+    using B = BlockNtt<LOGM, LOGE>;
+    allow_lds<k_pblocks_inv<LOGM, LOGE>>();
+    k_pblocks_inv<LOGM, LOGE><<<dim3(1u << (tb.log_n - LOGM), tb.k, items * 2), dim3(B::T), block_lds<LOGM, LOGE>(), s>>>(tb, acc, accp);
+    return hipGetLastError();
+  }
+};
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+
+hipError_t launch_ntt(const DevTables& tb, int log_r, uint64_t* x, int first, int nlimbs, int items, hipStream_t s) {
+  const int log_m = tb.log_n - log_r;
+  hipError_t e = hipSuccess;
+  if (log_r > 0) e = by_logr<ColsFwd>(log_r, tb, x, first, nlimbs, items, log_m, s);
+  if (e != hipSuccess) return e;
+  return by_logm<BlocksFwd>(log_m, tb, (const uint64_t*)x, x, first, nlimbs, items, 0, s);
+}
+
+hipError_t launch_intt(const DevTables& tb, int log_r, uint64_t* x, int first, int nlimbs, int items, hipStream_t s) {
+  const int log_m = tb.log_n - log_r;
+  hipError_t e = by_logm<BlocksInv>(log_m, tb, (const uint64_t*)x, x, first, nlimbs, items, log_r == 0 ? 1 : 0, s);
+  if (e != hipSuccess || log_r == 0) return e;
+  return by_logr<ColsInv>(log_r, tb, x, first, nlimbs, items, log_m, s);
+}
+
+hipError_t launch_intt_blocks(const DevTables& tb, int log_r, const uint64_t* src, uint64_t* dst, int nlimbs,
+                              int items, hipStream_t s) {
+  return by_logm<BlocksInv>(tb.log_n - log_r, tb, src, dst, 0, nlimbs, items, 0, s);
+}
+
+hipError_t launch_modup_cols(const DevTables& tb, int log_r, const uint64_t* t1, uint64_t* ext1, int j0, int nj,
+                             int nslots, int slot_stride, int tgt0, int tgt1, int items, hipStream_t s) {
+  return by_logr<ModupCols>(log_r, tb, t1, ext1, j0, nj, nslots, slot_stride, tgt0, tgt1, items, tb.log_n - log_r, s);
+}
+
+hipError_t launch_keymult_blocks(const DevTables& tb, int log_r, const uint64_t* d, const uint64_t* ext1,
+                                 const uint64_t* evk, uint64_t* acc, int j0, int j1, int nslots, int slot_stride,
+                                 int tgt0, int tgt1, int items, int accumulate, int finalize, hipStream_t s) {
+  return by_logm<KeymultBlocks>(tb.log_n - log_r, tb, d, ext1, evk, acc, j0, j1, nslots, slot_stride, tgt0, tgt1,
+                                items, accumulate, finalize, s);
+}
+
+hipError_t launch_moddown_cols(const DevTables& tb, int log_r, const uint64_t* accp, uint64_t* t2, int tgt0,
+                               int tgt1, int items, hipStream_t s) {
+  return by_logr<ModdownCols>(log_r, tb, accp, t2, tgt0, tgt1, items, tb.log_n - log_r, s);
+}
+
+hipError_t launch_moddown_blocks(const DevTables& tb, int log_r, const uint64_t* t2, const uint64_t* acc,
+                                 uint64_t* out, int tgt0, int tgt1, int items, hipStream_t s) {
+  return by_logm<ModdownBlocks>(tb.log_n - log_r, tb, t2, acc, out, tgt0, tgt1, items, s);
+}
+
+hipError_t launch_ext_blocks(const DevTables& tb, int log_r, uint64_t* ext, int items, hipStream_t s) {
+  return by_logm<ExtBlocks>(tb.log_n - log_r, tb, ext, items, s);
+}
+
+hipError_t launch_pblocks_inv(const DevTables& tb, int log_r, const uint64_t* acc, uint64_t* accp, int items,
+                              hipStream_t s) {
+  return by_logm<PBlocksInv>(tb.log_n - log_r, tb, acc, accp, items, s);
+}
+
+hipError_t launch_copy_digits(const DevTables& tb, const uint64_t* d, uint64_t* ext, int items, hipStream_t s) {
+  const unsigned n = 1u << tb.log_n;
+  k_copy_digits<<<dim3((n + 255) / 256, tb.ell, items), dim3(256), 0, s>>>(tb, d, ext);
+  return hipGetLastError();
+}
+
+hipError_t launch_bconv(const DevTables& tb, const uint64_t* src, int set, uint64_t* dst, int items, hipStream_t s) {
+  const unsigned n = 1u << tb.log_n;
+  int nd;
+  if (set < 0) {
+    nd = tb.ell;
+  } else {
+    const int lo = set * tb.alpha;
+    const int hi = lo + tb.alpha < tb.ell ? lo + tb.alpha : tb.ell;
+    nd = tb.nl - (hi - lo);
+  }
+  k_bconv<<<dim3((n + 255) / 256, nd, items), dim3(256), 0, s>>>(tb, src, dst, set);
+  return hipGetLastError();
+}
+
+hipError_t launch_keymult(const DevTables& tb, const uint64_t* ext, const uint64_t* evk, uint64_t* acc, int items,
+                          hipStream_t s) {
+  const unsigned n = 1u << tb.log_n;
+  k_keymult<<<dim3((n + 255) / 256, 2 * tb.nl, items), dim3(256), 0, s>>>(tb, ext, evk, acc);
+  return hipGetLastError();
+}
+
+}  // namespace ks

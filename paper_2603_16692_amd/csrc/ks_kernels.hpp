@@ -1,0 +1,35 @@
+// Host launchers of the KeySwitch kernels (ks_kernels.hip). Every launcher
+// only enqueues on stream `s` and returns the launch status.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ks_device.hpp"
+
+namespace ks {
+
+// Two-pass transforms of x [items][nlimbs][N], limb r over prime first + r.
+hipError_t launch_ntt(const DevTables& tb, int log_r, uint64_t* x, int first, int nlimbs, int items, hipStream_t s);
+hipError_t launch_intt(const DevTables& tb, int log_r, uint64_t* x, int first, int nlimbs, int items, hipStream_t s);
+// Inverse block pass only (stages log_n-1 .. log_r) of src [items][nlimbs][N] over primes 0..nlimbs-1.
+hipError_t launch_intt_blocks(const DevTables& tb, int log_r, const uint64_t* src, uint64_t* dst, int nlimbs,
+                              int items, hipStream_t s);
+hipError_t launch_modup_cols(const DevTables& tb, int log_r, const uint64_t* t1, uint64_t* ext1, int j0, int nj,
+                             int nslots, int slot_stride, int tgt0, int tgt1, int items, hipStream_t s);
+hipError_t launch_keymult_blocks(const DevTables& tb, int log_r, const uint64_t* d, const uint64_t* ext1,
+                                 const uint64_t* evk, uint64_t* acc, int j0, int j1, int nslots, int slot_stride,
+                                 int tgt0, int tgt1, int items, int accumulate, int finalize, hipStream_t s);
+hipError_t launch_moddown_cols(const DevTables& tb, int log_r, const uint64_t* accp, uint64_t* t2, int tgt0,
+                               int tgt1, int items, hipStream_t s);
+hipError_t launch_moddown_blocks(const DevTables& tb, int log_r, const uint64_t* t2, const uint64_t* acc,
+                                 uint64_t* out, int tgt0, int tgt1, int items, hipStream_t s);
+hipError_t launch_ext_blocks(const DevTables& tb, int log_r, uint64_t* ext, int items, hipStream_t s);
+hipError_t launch_pblocks_inv(const DevTables& tb, int log_r, const uint64_t* acc, uint64_t* accp, int items,
+                              hipStream_t s);
+hipError_t launch_copy_digits(const DevTables& tb, const uint64_t* d, uint64_t* ext, int items, hipStream_t s);
+hipError_t launch_bconv(const DevTables& tb, const uint64_t* src, int set, uint64_t* dst, int items, hipStream_t s);
+hipError_t launch_keymult(const DevTables& tb, const uint64_t* ext, const uint64_t* evk, uint64_t* acc, int items,
+                          hipStream_t s);
+
+}  // namespace ks

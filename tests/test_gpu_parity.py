@@ -1,0 +1,257 @@
+"""Bit-exact parity of every C-ABI call of libks against the CPU oracle.
+
+Inputs are the seeded synthetic residues of ``synth`` and keys from the
+oracle's key generator; expected values come from the oracle only. Sizes
+span several workgroup tiles, odd limb counts and batch sizes, every NTT
+split, every dataflow, and the four benchmark parameter sets at full size.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import ciphertext_batch, uniform_residues
+
+import pins
+from conftest import CONFIGS
+from gpu_util import dev, empty, first_mismatch, host
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [(3, 12, 7), (2, 10, 5), (4, 11, 8), (1, 9, 3), (3, 14, 9)]
+
+
+@pytest.fixture(scope="module")
+def ks():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2603_16692_amd as k
+    return k
+
+
+_params_cache = {}
+
+
+def params(ks, dnum, log_n, ell):
+    key = (dnum, log_n, ell)
+    if key not in _params_cache:
+        _params_cache[key] = (ks.KsParams(dnum, log_n, ell), oracle.Params(dnum, log_n, ell))
+    return _params_cache[key]
+
+
+def assert_same(gpu, ref, what):
+    mm = first_mismatch(gpu, ref)
+    assert mm is None, f"{what}: first mismatch {mm}"
+
+
+@pytest.mark.parametrize("dnum,log_n,ell", SMALL + [v[:3] for v in CONFIGS.values()])
+def test_params_match_oracle(ks, dnum, log_n, ell):
+    G, P = params(ks, dnum, log_n, ell)
+    assert G.moduli == P.moduli and G.psi == P.psi
+    assert (G.k, G.alpha, G.ndig, G.n) == (P.k, P.alpha, P.ndig, P.n)
+
+
+@pytest.mark.parametrize("dnum,log_n,ell", SMALL + [v[:3] for v in CONFIGS.values()])
+def test_ntt_intt(ks, dnum, log_n, ell):
+    G, P = params(ks, dnum, log_n, ell)
+    batch = 3 if log_n < 16 else 1
+    x = np.stack([uniform_residues(11 + b, P.moduli, P.n) for b in range(batch)])
+    ref_f = np.empty_like(x)
+    ref_i = np.empty_like(x)
+    for b in range(batch):
+        for t in range(P.nl):
+            ref_f[b, t] = oracle.ntt(P.moduli[t], P.psi[t], log_n, x[b, t])
+            ref_i[b, t] = oracle.intt(P.moduli[t], P.psi[t], log_n, x[b, t])
+    y = dev(x)
+    G.ntt(y, 0, P.nl, batch)
+    assert_same(host(y), ref_f, "ntt")
+    y = dev(x)
+    G.intt(y, 0, P.nl, batch)
+    assert_same(host(y), ref_i, "intt")
+    # a sub-range of the basis: the P limbs only
+    y = dev(np.ascontiguousarray(x[:, P.ell:]))
+    G.ntt(y, P.ell, P.k, batch)
+    assert_same(host(y), ref_f[:, P.ell:], "ntt on P limbs")
+
+
+@pytest.mark.parametrize("dnum,log_n,ell", SMALL + [v[:3] for v in CONFIGS.values()])
+def test_bconv(ks, dnum, log_n, ell):
+    G, P = params(ks, dnum, log_n, ell)
+    batch = 2
+    for j in list(range(P.ndig)) + [-1]:
+        src_mod = P.p if j < 0 else [P.moduli[i] for i in P.digit(j)]
+        x = np.stack([uniform_residues(30 + b + 3 * j, src_mod, P.n) for b in range(batch)])
+        ref = oracle.bconv(P, j, x, batch)
+        out = empty(ref.shape)
+        G.bconv(dev(x), j, out, batch)
+        assert_same(host(out), ref, f"bconv set {j}")
+
+
+@pytest.mark.parametrize("dnum,log_n,ell", SMALL + [(2, 13, 6), (2, 15, 10), (4, 16, 32)])
+def test_modup_keymult_moddown(ks, dnum, log_n, ell):
+    G, P = params(ks, dnum, log_n, ell)
+    batch = 3 if log_n < 16 else 1
+    d = ciphertext_batch(P.q, P.n, batch)
+    _, _, evk = oracle.keygen(P, h=min(64, P.n // 2))
+    ext_ref = oracle.modup(P, d, batch)
+    acc_ref = oracle.keymult(P, ext_ref, evk, batch)
+    out_ref = oracle.moddown(P, acc_ref, batch)
+    ws = G.workspace(batch, ks.make_plan(ks.STAGED))
+    ext = empty(ext_ref.shape)
+    G.modup(dev(d), ext, batch, ws)
+    assert_same(host(ext), ext_ref, "modup")
+    acc = empty(acc_ref.shape)
+    G.keymult(dev(ext_ref), dev(evk), acc, batch)
+    assert_same(host(acc), acc_ref, "keymult")
+    acc_in = dev(acc_ref)
+    out = empty(out_ref.shape)
+    G.moddown(acc_in, out, batch, ws)
+    assert_same(host(out), out_ref, "moddown")
+    assert_same(host(acc_in), acc_ref, "moddown leaves acc unchanged")
+
+
+def _plans(ks, P, log_n):
+    plans = []
+    for log_r in range(0, 5):
+        log_m = log_n - log_r
+        if log_m < 3 or log_m > 14:
+            continue
+        for df, chunks in [(ks.DSOB, 1), (ks.DPOB, 1), (ks.DSOC, 2), (ks.DPOC, 3), (ks.STAGED, 1)]:
+            chunks = min(chunks, P.ell)
+            plans.append(ks.make_plan(df, chunks, log_r))
+    return plans
+
+
+@pytest.mark.parametrize("dnum,log_n,ell", SMALL)
+def test_keyswitch_every_plan(ks, dnum, log_n, ell):
+    G, P = params(ks, dnum, log_n, ell)
+    batch = 3
+    d = ciphertext_batch(P.q, P.n, batch)
+    _, _, evk = oracle.keygen(P, h=min(64, P.n // 2))
+    ref = oracle.keyswitch(P, d, evk, batch)
+    dd, ee = dev(d), dev(evk)
+    for plan in _plans(ks, P, log_n):
+        out = empty(ref.shape)
+        ws = G.workspace(batch, plan)
+        G.keyswitch(dd, ee, out, batch, ws, plan)
+        assert_same(host(out), ref, f"keyswitch {plan}")
+
+
+_full_cache = {}
+
+
+def full_case(ks, name):
+    if name not in _full_cache:
+        dnum, log_n, ell, batch = CONFIGS[name]
+        G, P = params(ks, dnum, log_n, ell)
+        s, s2, evk = oracle.keygen(P, h=64)
+        d = ciphertext_batch(P.q, P.n, batch)
+        ref = oracle.keyswitch(P, d, evk, batch)
+        _full_cache[name] = (G, P, s, s2, evk, d, ref, batch)
+    return _full_cache[name]
+
+
+@pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3"])
+def test_keyswitch_benchmark_sizes(ks, name):
+    G, P, s, s2, evk, d, ref, batch = full_case(ks, name)
+    dd, ee = dev(d), dev(evk)
+    plans = [None, ks.make_plan(ks.DSOB), ks.make_plan(ks.DPOC, 4), ks.make_plan(ks.DSOC, 2)]
+    for plan in plans:
+        out = empty(ref.shape)
+        ws = G.workspace(batch, plan)
+        G.keyswitch(dd, ee, out, batch, ws, plan)
+        got = host(out)
+        assert_same(got, ref, f"{name} keyswitch {plan}")
+        del ws, out
+    ok, m = pins.decrypt_ok(P, d, got, s, s2, 64, batch)
+    assert ok, f"decryption error {m} above bound {oracle.ks_bound(P, 64)}"
+
+
+def test_batch_item_equals_single(ks):
+    G, P = params(ks, 3, 12, 7)
+    d = ciphertext_batch(P.q, P.n, 5)
+    _, _, evk = oracle.keygen(P, h=64)
+    dd, ee = dev(d), dev(evk)
+    out = empty((5, 2, P.ell, P.n))
+    G.keyswitch(dd, ee, out, 5, G.workspace(5))
+    allb = host(out)
+    for b in range(5):
+        one = empty((1, 2, P.ell, P.n))
+        G.keyswitch(dev(d[b:b + 1]), ee, one, 1, G.workspace(1))
+        assert_same(host(one)[0], allb[b], f"item {b}")
+
+
+def test_two_streams_concurrently(ks):
+    G, P = params(ks, 2, 15, 10)
+    d = ciphertext_batch(P.q, P.n, 4)
+    _, _, evk = oracle.keygen(P, h=64)
+    ref = oracle.keyswitch(P, d, evk, 4)
+    ee = dev(evk)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs, keep = [], []
+    for i, st in enumerate(streams):
+        with torch.cuda.stream(st):
+            dd = dev(d[2 * i:2 * i + 2])
+            ws = G.workspace(2)
+            out = empty((2, 2, P.ell, P.n))
+            for _ in range(3):
+                G.keyswitch(dd, ee, out, 2, ws, stream=st)
+            outs.append(out)
+            keep += [dd, ws]
+    torch.cuda.synchronize()
+    for i in range(2):
+        assert_same(host(outs[i]), ref[2 * i:2 * i + 2], f"stream {i}")
+
+
+def test_zero_input_gives_zero(ks):
+    G, P = params(ks, 2, 13, 6)
+    _, _, evk = oracle.keygen(P, h=64)
+    d = np.zeros((2, P.ell, P.n), dtype=np.uint64)
+    out = empty((2, 2, P.ell, P.n))
+    G.keyswitch(dev(d), dev(evk), out, 2, G.workspace(2))
+    assert not host(out).any()
+
+
+def test_argument_errors(ks):
+    G, P = params(ks, 2, 13, 6)
+    ws = G.workspace(1)
+    d = empty((1, P.ell, P.n))
+    evk = empty((P.ndig, 2, P.nl, P.n))
+    out = empty((1, 2, P.ell, P.n))
+    with pytest.raises(ks.KsError) as e:
+        G.keyswitch(d, evk, None, 1, ws)
+    assert e.value.code == ks.KS_ENULL
+    bad = empty(P.ell * P.n + 1)[1:]
+    with pytest.raises(ks.KsError) as e:
+        G.keyswitch(bad, evk, out, 1, ws)
+    assert e.value.code == ks.KS_EALIGN
+    with pytest.raises(ks.KsError) as e:
+        G.keyswitch(d, evk, out, 1, ws, ks.make_plan(ks.DSOC, 0))
+    assert e.value.code == ks.KS_EUNSUP
+    with pytest.raises(ks.KsError) as e:
+        G.keyswitch(d, evk, out, 1, ws, ks.make_plan(ks.DPOB, 1, 9))
+    assert e.value.code == ks.KS_EUNSUP
+    with pytest.raises(ks.KsError) as e:
+        G.ntt(d, P.nl - 1, 2, 1)
+    assert e.value.code == ks.KS_EINVAL
+    with pytest.raises(ks.KsError) as e:
+        G.bconv(d, P.ndig, out, 1)
+    assert e.value.code == ks.KS_EINVAL
+    with pytest.raises(ks.KsError) as e:
+        ks.KsParams(3, 13, 2)
+    assert e.value.code == ks.KS_EINVAL
+    with pytest.raises(ks.KsError) as e:
+        ks.KsParams(1, 18, 2)
+    assert e.value.code == ks.KS_EINVAL
+    # batch 0 is a no-op
+    G.keyswitch(d, evk, out, 0, ws)
+
+
+def test_launch_counts_follow_table_iii(ks):
+    # launches: DSOB O(d), DPOB O(1), DSOC O(dc), DPOC O(c)
+    G, P = params(ks, 4, 16, 32)
+    d = P.ndig
+    assert G.launch_count(1, ks.make_plan(ks.DPOB)) == 5
+    assert G.launch_count(1, ks.make_plan(ks.DSOB)) == 1 + 2 * d + 2
+    for c in (2, 3, 5):
+        assert G.launch_count(1, ks.make_plan(ks.DPOC, c)) == 1 + 2 * c + 2 * c
+        assert G.launch_count(1, ks.make_plan(ks.DSOC, c)) == 1 + 2 * d * c + 2 * c
