@@ -134,6 +134,20 @@ int ks_keyswitch(const ks_params* p, const uint64_t* d, const uint64_t* evk, uin
 /* Number of kernel launches ks_keyswitch enqueues for (batch, plan). */
 int ks_launch_count(const ks_params* p, int batch, const ks_plan* plan);
 
+/* HIP-graph replay of one KeySwitch. ks_graph_create runs
+ * ks_keyswitch(p, d, evk, out, batch, plan, ws) once eagerly on `stream` (a
+ * non-null hipStream_t), then captures the same call into a HIP graph and
+ * instantiates it. Its pointers are baked into the graph: each
+ * ks_graph_launch(g, stream) recomputes out from the current contents of d and
+ * evk, with one graph launch instead of the plan's kernel launches. The graph
+ * holds no memset node. Destroy with ks_graph_destroy; the caller keeps every
+ * buffer alive while the graph is in use. Graphs do not record launch traces. */
+typedef struct ks_graph ks_graph;
+int ks_graph_create(const ks_params* p, const uint64_t* d, const uint64_t* evk, uint64_t* out, int batch,
+                    const ks_plan* plan, void* ws, void* stream, ks_graph** graph);
+int ks_graph_launch(ks_graph* graph, void* stream);
+void ks_graph_destroy(ks_graph* graph);
+
 /* Kernel kinds of the launch trace. */
 #define KS_K_INTT_D 0         /* inverse block pass of d (first step of ModUp) */
 #define KS_K_MODUP_COLS 1     /* ModUp: inverse column pass, BConv, forward column pass */

@@ -68,12 +68,18 @@ _lib.ks_last_hip_error.restype = ctypes.c_char_p
 _lib.ks_trace_begin.argtypes = [ctypes.POINTER(_vp), _i, ctypes.c_uint]
 _lib.ks_trace_end.argtypes = [ctypes.POINTER(_i), _i]
 
+_lib.ks_graph_create.argtypes = [_vp, _vp, _vp, _vp, _i, ctypes.POINTER(Plan), _vp, _vp, ctypes.POINTER(_vp)]
+_lib.ks_graph_launch.argtypes = [_vp, _vp]
+_lib.ks_graph_destroy.argtypes = [_vp]
+_lib.ks_graph_destroy.restype = None
+
 KIND_NAMES = ["intt_d_blocks", "modup_cols", "keymult_blocks", "moddown_cols", "moddown_blocks", "ext_blocks",
               "pblocks_inv", "copy_digits", "keymult", "bconv", "ntt"]
 
 EXPORTED = ["ks_params_create", "ks_params_destroy", "ks_params_info", "ks_workspace_bytes", "ks_default_plan",
             "ks_ntt", "ks_intt", "ks_bconv", "ks_modup", "ks_keymult", "ks_moddown", "ks_keyswitch",
-            "ks_launch_count", "ks_strerror", "ks_last_hip_error", "ks_trace_begin", "ks_trace_end"]
+            "ks_launch_count", "ks_strerror", "ks_last_hip_error", "ks_trace_begin", "ks_trace_end",
+            "ks_graph_create", "ks_graph_launch", "ks_graph_destroy"]
 
 
 class KsError(RuntimeError):
@@ -182,11 +188,40 @@ class KsParams:
         _check(_lib.ks_keyswitch(self._h, _ptr(d), _ptr(evk), _ptr(out), batch,
                                  ctypes.byref(plan) if plan else None, _ptr(ws), _stream(stream)), "ks_keyswitch")
 
+    def graph(self, d, evk, out, batch, ws, plan: Plan = None, stream=None) -> "Graph":
+        """Capture one KeySwitch on these buffers into a replayable HIP graph."""
+        return Graph(self, d, evk, out, batch, ws, plan, stream)
+
     # ------------------------------------------------------------ helpers
     def shapes(self, batch: int):
         n, ell, nl, nd = self.n, self.ell, self.nl, self.ndig
         return {"d": (batch, ell, n), "ext": (batch, nd, nl, n), "evk": (nd, 2, nl, n),
                 "acc": (batch, 2, nl, n), "out": (batch, 2, ell, n)}
+
+
+class Graph:
+    """A captured KeySwitch (ks_graph_*); keeps its buffers alive while it lives."""
+
+    def __init__(self, params, d, evk, out, batch, ws, plan=None, stream=None):
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        if stream.cuda_stream == 0:
+            raise ValueError("graph capture needs a non-default stream")
+        h = _vp()
+        _check(_lib.ks_graph_create(params._h, _ptr(d), _ptr(evk), _ptr(out), batch,
+                                    ctypes.byref(plan) if plan else None, _ptr(ws), _stream(stream), ctypes.byref(h)),
+               "ks_graph_create")
+        self._h = h
+        self._keep = (params, d, evk, out, ws, plan)
+
+    def launch(self, stream=None):
+        _check(_lib.ks_graph_launch(self._h, _stream(stream)), "ks_graph_launch")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.ks_graph_destroy(h)
+            self._h = None
 
 
 class HipEvents:
@@ -230,10 +265,12 @@ class HipEvents:
         return float(ms.value)
 
     def __del__(self):
-        h = HipEvents._hip
-        if h is not None:
+        try:
+            h = HipEvents._hip
             for i in range(getattr(self, "count", 0)):
                 h.hipEventDestroy(self.ev[i])
+        except Exception:  # interpreter shutdown: the runtime may be gone
+            pass
 
 
 def trace_begin(events: HipEvents, kind_mask: int = 0xFFFFFFFF) -> None:

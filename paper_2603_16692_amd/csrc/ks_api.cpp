@@ -69,11 +69,8 @@ int check_ptr(const void* p) {
 
 int default_log_r(int log_n) { return log_n > 13 ? log_n - 13 : 0; }
 
-constexpr size_t kLdsBytes = 160 * 1024;
-constexpr int kColThreads = 64;
-
 // Plan validity for these parameters: the NTT split must be compiled and the
-// BConv staging of the column kernels must fit in LDS.
+// BConv sources of the column kernels must fit their register staging.
 int resolve_plan(const ks_params* p, const ks_plan* in, ks_plan& out) {
   if (in) {
     out = *in;
@@ -85,10 +82,8 @@ int resolve_plan(const ks_params* p, const ks_plan* in, ks_plan& out) {
   if (out.log_r == 0) out.log_r = default_log_r(p->hp.log_n);
   if (out.log_r < 0) out.log_r = 0;
   const int log_m = p->hp.log_n - out.log_r;
-  if (out.log_r > 4 || log_m < 3 || log_m > 14) return KS_EUNSUP;
-  const size_t R = (size_t)1 << out.log_r;
-  const size_t stage = (size_t)std::max(p->hp.alpha, p->hp.k) * R * kColThreads * sizeof(uint64_t);
-  if (stage > kLdsBytes) return KS_EUNSUP;
+  if (out.log_r > 5 || log_m < 3 || log_m > 14) return KS_EUNSUP;
+  if (ks::stage_cap(p->hp.alpha, out.log_r) == 0 || ks::stage_cap(p->hp.k, out.log_r) == 0) return KS_EUNSUP;
   if (out.dataflow == KS_DSOC || out.dataflow == KS_DPOC) {
     if (out.chunks < 1 || out.chunks > 64 || out.chunks > p->hp.ell) return KS_EUNSUP;
   } else {
@@ -250,6 +245,12 @@ int ks_params_create(int dnum, int log_n, int ell, ks_params** out) {
   rebase(p->tb.dn_pinv);
   rebase(p->tb.up_hinv);
   rebase(p->tb.dn_hinv);
+  rebase(p->tb.twf_d);
+  rebase(p->tb.twi_d);
+  rebase(p->tb.up_pre_d);
+  rebase(p->tb.up_mat_d);
+  rebase(p->tb.dn_mat_d);
+  rebase(p->tb.dn_pinv_d);
   *out = p;
   return KS_OK;
 }
@@ -419,6 +420,56 @@ const char* ks_strerror(int code) {
 }
 
 const char* ks_last_hip_error(void) { return g_hip_error.c_str(); }
+
+struct ks_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+int ks_graph_create(const ks_params* p, const uint64_t* d, const uint64_t* evk, uint64_t* out, int batch,
+                    const ks_plan* plan, void* ws, void* stream, ks_graph** graph) {
+  if (!p || !graph) return KS_ENULL;
+  *graph = nullptr;
+  if (!stream) return KS_ENULL;  // the legacy null stream cannot be captured
+  if (batch < 1) return KS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  // one eager call: validates the arguments and sets per-kernel attributes
+  int rc = ks_keyswitch(p, d, evk, out, batch, plan, ws, stream);
+  if (rc != KS_OK) return rc;
+  ks_graph* g = new (std::nothrow) ks_graph;
+  if (!g) return KS_ENOMEM;
+  Trace saved = g_trace;
+  g_trace = Trace{};
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    rc = ks_keyswitch(p, d, evk, out, batch, plan, ws, stream);
+    hipGraph_t captured = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(s, &captured);
+    g->graph = captured;
+    if (rc == KS_OK && e2 != hipSuccess) e = e2;
+  }
+  g_trace = saved;
+  if (e == hipSuccess && rc == KS_OK) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess || rc != KS_OK) {
+    ks_graph_destroy(g);
+    return rc != KS_OK ? rc : hip_fail(e);
+  }
+  *graph = g;
+  return KS_OK;
+}
+
+int ks_graph_launch(ks_graph* graph, void* stream) {
+  if (!graph || !graph->exec) return KS_ENULL;
+  const hipError_t e = hipGraphLaunch(graph->exec, (hipStream_t)stream);
+  return e == hipSuccess ? KS_OK : hip_fail(e);
+}
+
+void ks_graph_destroy(ks_graph* graph) {
+  if (!graph) return;
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  delete graph;
+}
 
 int ks_trace_begin(void** events, int capacity, unsigned kind_mask) {
   if (!events && capacity > 0) return KS_ENULL;

@@ -1,14 +1,24 @@
 // Device-side data structures, modular arithmetic and NTT building blocks.
 //
-// Residues are uint64. Products by fixed constants (twiddles, BConv
-// matrices, scale factors) use Shoup's method with a precomputed companion
-// w' = floor(w * 2^64 / q); products of two variables (KeyMult) use
-// Montgomery's REDC with R = 2^64 followed by a multiplication by
-// R^2 mod q. Transforms keep Harvey's lazy ranges: forward butterflies take
-// and return values in [0, 4q), inverse butterflies in [0, 2q), which needs
-// 4q < 2^64 (every prime here is below 2^60).
+// Two arithmetics share the transform code:
+//  * ArF, for the Q primes (q < 2^50): residues are held as integer-valued
+//    doubles and multiplied with FP64 FMA. For a product p = a*b,
+//    h = fl(a*b), l = fma(a, b, -h) gives p = h + l exactly; k = rint(h * fl(1/q))
+//    is within 1/2 + 1.5*2^-52*|p|/q of p/q, and r = fma(-k, q, h) + l = p - k*q
+//    exactly whenever |p| <= 2^103. So |r| <= q/2 + 1.5*2^-52*|p|. The
+//    transform keeps every value within 2q (for q in [2^49, 2^50)), where
+//    products of a value and a balanced twiddle (|w| <= q/2) stay below
+//    q^2 < 2^100. MI355X runs FP64 FMA at the full vector rate, which makes
+//    this about three times faster than 64-bit integer products.
+//  * ArI, for the P primes (p < 2^60): uint64 residues; products by fixed
+//    constants use Shoup's method (w' = floor(w * 2^64 / q)), products of two
+//    variables Montgomery's REDC with R = 2^64. Forward butterflies keep
+//    Harvey's [0, 4q) range, inverse butterflies [0, 2q).
+// Between kernels, Q-limb data is stored as canonical uint64 residues and
+// P-limb data in the lazy integer ranges stated at each kernel.
 #pragma once
 #include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 namespace ks {
@@ -20,8 +30,11 @@ struct LimbC {
   uint64_t mont_ninv;  // -q^-1 mod 2^64
   uint64_t r2;         // 2^128 mod q
   uint64_t ninv, ninv_s;
-  uint64_t red_s;      // floor(2^64 / q): Shoup companion of 1, reduces any x < 2^64
-  uint64_t pad;
+  uint64_t red_s;      // floor(2^64 / q): Shoup companion of 1
+  double qd;           // q as a double (exact for the Q primes)
+  double qinv;         // fl(1 / q)
+  double ninv_d;       // balanced N^-1 mod q (Q primes)
+  double pad0, pad1;
 };
 
 // Every table of one parameter set. Pointers are device addresses after
@@ -31,18 +44,26 @@ struct DevTables {
   const LimbC* limb;        // [nl]
   const uint64_t* twf;      // [nl][N][2]: (psi^brv(i), Shoup) for i in [1, N)
   const uint64_t* twi;      // [nl][N][2]: (psi^-brv(i), Shoup)
+  const double* twf_d;      // [ell][N]: balanced psi^brv(i) (Q primes)
+  const double* twi_d;      // [ell][N]: balanced psi^-brv(i)
   const uint64_t* up_pre;   // [ell][2]: N^-1 * [(D_j/q_i)^-1]_{q_i}, Shoup (j = digit of i)
+  const double* up_pre_d;   // [ell]: the same, balanced double
   const uint64_t* up_mat;   // [ell][nl][2]: [D_j/q_i]_t with its Shoup companion mod t
+  const double* up_mat_d;   // [ell][ell]: [D_j/q_i]_{q_t}, balanced double (Q targets)
   const uint64_t* dn_pre;   // [k][2]: N^-1 * [(P/p_m)^-1]_{p_m}, Shoup
   const uint64_t* dn_mat;   // [k][ell][2]: [P/p_m]_{q_i}, Shoup mod q_i
+  const double* dn_mat_d;   // [k][ell][2]: balanced [2^30 * P/p_m]_{q_i}, [P/p_m]_{q_i}
   const uint64_t* dn_pinv;  // [ell][2]: [P^-1]_{q_i}, Shoup
+  const double* dn_pinv_d;  // [ell]: balanced [P^-1]_{q_i}
   const uint64_t* up_hinv;  // [ell][2]: [(D_j/q_i)^-1]_{q_i}, Shoup (no N^-1)
   const uint64_t* dn_hinv;  // [k][2]: [(P/p_m)^-1]_{p_m}, Shoup (no N^-1)
 };
 
+// ------------------------------------------------------------ integers
+
 __device__ __forceinline__ uint64_t mul_shoup(uint64_t a, uint64_t w, uint64_t ws, uint64_t q) {
   // a < 2^64, w < q: returns a*w mod q in [0, 2q).
-  uint64_t hi = __umul64hi(a, ws);
+  const uint64_t hi = __umul64hi(a, ws);
   return a * w - hi * q;
 }
 
@@ -55,11 +76,48 @@ __device__ __forceinline__ uint64_t reduce4(uint64_t x, uint64_t q, uint64_t two
 
 // Montgomery REDC of a*b for a*b < q * 2^64: returns a*b*2^-64 mod q in [0, 2q).
 __device__ __forceinline__ uint64_t mont_mul(uint64_t a, uint64_t b, uint64_t q, uint64_t ninv) {
-  uint64_t lo = a * b, hi = __umul64hi(a, b);
-  uint64_t m = lo * ninv;
-  uint64_t mh = __umul64hi(m, q);
+  const uint64_t lo = a * b, hi = __umul64hi(a, b);
+  const uint64_t m = lo * ninv;
+  const uint64_t mh = __umul64hi(m, q);
   return hi + mh + (lo != 0 ? 1 : 0);
 }
+
+// --------------------------------------------------------------- FP64
+
+// a*b mod q as an integer-valued double with |r| <= q/2 + 1.5*2^-52*|a*b|,
+// for |a*b| <= 2^103 (see the header comment).
+__device__ __forceinline__ double f_mul(double a, double b, double q, double qinv) {
+  const double h = a * b;
+  const double l = __fma_rn(a, b, -h);
+  const double k = __builtin_rint(h * qinv);
+  const double r = __fma_rn(-k, q, h);
+  return r + l;
+}
+
+// x mod q into [-q/2 - 1, q/2 + 1], for integer-valued |x| < 2^53.
+__device__ __forceinline__ double f_red(double x, double q, double qinv) {
+  return __fma_rn(-__builtin_rint(x * qinv), q, x);
+}
+
+// Exact conversion of an integer 0 <= v < 2^52.
+__device__ __forceinline__ double u2d(uint64_t v) {
+  return __longlong_as_double((long long)(v | 0x4330000000000000ull)) - 4503599627370496.0;
+}
+
+// Canonical residue of an integer-valued |x| < 2^53, as uint64.
+__device__ __forceinline__ uint64_t f_canon(double x, double q, double qinv) {
+  double r = f_red(x, q, qinv);
+  r = r < 0.0 ? r + q : r;
+  return (uint64_t)__double_as_longlong(r + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
+}
+
+// Canonical residue in [0, q) as a double.
+__device__ __forceinline__ double f_canon_d(double x, double q, double qinv) {
+  const double r = f_red(x, q, qinv);
+  return r < 0.0 ? r + q : r;
+}
+
+// ------------------------------------------------------ arithmetics
 
 struct Tw {
   uint64_t w, ws;
@@ -70,54 +128,81 @@ __device__ __forceinline__ Tw load_tw(const uint64_t* table, uint32_t idx) {
   return Tw{v.x, v.y};
 }
 
-// Forward (Cooley-Tukey) butterfly: X, Y in [0, 4q) -> X + W*Y, X - W*Y in [0, 4q).
-__device__ __forceinline__ void bf_fwd(uint64_t& X, uint64_t& Y, Tw t, uint64_t q, uint64_t two_q) {
-  uint64_t x = X >= two_q ? X - two_q : X;
-  uint64_t v = mul_shoup(Y, t.w, t.ws, q);
-  X = x + v;
-  Y = x - v + two_q;
-}
+// Integer arithmetic of one P limb; `tw` is its (w, Shoup) table.
+struct ArI {
+  using T = uint64_t;
+  uint64_t q, two_q;
+  const uint64_t* tw;
+  // Forward (Cooley-Tukey): X, Y in [0, 4q) -> X + W*Y, X - W*Y in [0, 4q).
+  __device__ __forceinline__ void fwd(T& X, T& Y, uint32_t idx) const {
+    const Tw t = load_tw(tw, idx);
+    const uint64_t x = X >= two_q ? X - two_q : X;
+    const uint64_t v = mul_shoup(Y, t.w, t.ws, q);
+    X = x + v;
+    Y = x - v + two_q;
+  }
+  // Inverse (Gentleman-Sande): X, Y in [0, 2q) -> X + Y, W*(X - Y) in [0, 2q).
+  __device__ __forceinline__ void inv(T& X, T& Y, uint32_t idx) const {
+    const Tw t = load_tw(tw, idx);
+    uint64_t s = X + Y;
+    s = s >= two_q ? s - two_q : s;
+    const uint64_t d = X - Y + two_q;
+    X = s;
+    Y = mul_shoup(d, t.w, t.ws, q);
+  }
+};
 
-// Inverse (Gentleman-Sande) butterfly: X, Y in [0, 2q) -> X + Y, W*(X - Y) in [0, 2q).
-__device__ __forceinline__ void bf_inv(uint64_t& X, uint64_t& Y, Tw t, uint64_t q, uint64_t two_q) {
-  uint64_t s = X + Y;
-  s = s >= two_q ? s - two_q : s;
-  uint64_t d = X - Y + two_q;
-  X = s;
-  Y = mul_shoup(d, t.w, t.ws, q);
-}
+// FP64 arithmetic of one Q limb; `tw` is its balanced twiddle table.
+// Invariant: every value entering a butterfly satisfies |x| <= 2q.
+struct ArF {
+  using T = double;
+  double q, qinv;
+  const double* tw;
+  // X <- red(X) (|X| <= q/2 + 1); V = W*Y with |V| <= q/2 + 0.75*2^-52*2q*q <= 0.875q;
+  // outputs within 1.375q + 1.
+  __device__ __forceinline__ void fwd(T& X, T& Y, uint32_t idx) const {
+    const double w = tw[idx];
+    const double x = f_red(X, q, qinv);
+    const double v = f_mul(Y, w, q, qinv);
+    X = x + v;
+    Y = x - v;
+  }
+  // X + Y reduced (|.| <= q/2 + 1); W*(X - Y) with |X - Y| <= 4q: |.| <= q/2 + 0.75q.
+  __device__ __forceinline__ void inv(T& X, T& Y, uint32_t idx) const {
+    const double w = tw[idx];
+    const double s = X + Y, d = X - Y;
+    X = f_red(s, q, qinv);
+    Y = f_mul(d, w, q, qinv);
+  }
+};
 
 // One subproblem of 2^K elements in registers. Local stage rho pairs
 // elements at distance 2^(K-1-rho); the twiddle of local group g is entry
 // (base << rho) + g of the bit-reversed table, where `base` is the table
 // index of the subproblem at its first stage (the butterfly tree of the
 // transform numbers node u's children 2u and 2u+1).
-template <int K>
-__device__ __forceinline__ void sub_fwd(uint64_t* x, const uint64_t* tw, uint32_t base, uint64_t q,
-                                        uint64_t two_q) {
+template <int K, class Ar>
+__device__ __forceinline__ void sub_fwd(const Ar& A, typename Ar::T* x, uint32_t base) {
 #pragma unroll
   for (int rho = 0; rho < K; ++rho) {
     const int dist = 1 << (K - 1 - rho);
 #pragma unroll
     for (int j = 0; j < (1 << K); ++j) {
       if (j & dist) continue;
-      const uint32_t idx = (base << rho) + (uint32_t)(j >> (K - rho));
-      bf_fwd(x[j], x[j + dist], load_tw(tw, idx), q, two_q);
+      A.fwd(x[j], x[j + dist], (base << rho) + (uint32_t)(j >> (K - rho)));
     }
   }
 }
 
-template <int K>
-__device__ __forceinline__ void sub_inv(uint64_t* x, const uint64_t* tw, uint32_t base, uint64_t q,
-                                        uint64_t two_q) {
+template <int K, class Ar>
+__device__ __forceinline__ void sub_inv(const Ar& A, typename Ar::T* x, uint32_t base) {
 #pragma unroll
   for (int rho = K - 1; rho >= 0; --rho) {
     const int dist = 1 << (K - 1 - rho);
 #pragma unroll
     for (int j = 0; j < (1 << K); ++j) {
       if (j & dist) continue;
-      const uint32_t idx = (base << rho) + (uint32_t)(j >> (K - rho));
-      bf_inv(x[j], x[j + dist], load_tw(tw, idx), q, two_q);
+      A.inv(x[j], x[j + dist], (base << rho) + (uint32_t)(j >> (K - rho)));
     }
   }
 }
@@ -133,9 +218,12 @@ __device__ __forceinline__ int lds_pad(int x) { return x + (x >> 4); }
 // size k, register u*2^k + j of thread tid holds element
 //   x = hi * (M >> s0) + lo + j * L,  L = M >> (s0 + k),  p = tid + u*T,
 //   lo = p mod L, hi = p / L.
-// The first round's positions ("FR": x = p + j*(M >> K1)) are coalesced for
-// global loads and stores; the last round's ("LR": x = tid*E + j) give each
-// thread E contiguous elements.
+// "FR" is the first round's layout (x = p + j*(M >> K1)); "CL" is the
+// coalesced layout x = tid + i*T. Forward transforms take FR and return CL;
+// inverse transforms take CL and return FR. Both layouts give consecutive
+// threads consecutive addresses for every register, so global loads and
+// stores at either end are coalesced; the last round's own layout
+// (x = tid*E + j) is transposed through LDS.
 template <int LOGM, int LOGE>
 struct BlockNtt {
   static constexpr int M = 1 << LOGM;
@@ -149,7 +237,6 @@ struct BlockNtt {
   __device__ static constexpr int round_s0(int r) { return r == 0 ? 0 : K1 + (r - 1) * LOGE; }
   __device__ static constexpr int round_k(int r) { return r == 0 ? K1 : LOGE; }
 
-  // Element index of register (u, j) in round r.
   __device__ static __forceinline__ int pos(int r, int tid, int u, int j) {
     const int s0 = round_s0(r), k = round_k(r);
     const int p = tid + u * T;
@@ -164,69 +251,69 @@ struct BlockNtt {
     const int L = M >> (s0 + k);
     return (B0 << s0) + (uint32_t)(p / L);
   }
-  __device__ static __forceinline__ int fr_pos(int tid, int i) {  // register i in the FR layout
-    return pos(0, tid, i >> K1, i & ((1 << K1) - 1));
-  }
-  __device__ static __forceinline__ int lr_pos(int tid, int i) { return tid * E + i; }
+  __device__ static __forceinline__ int fr_pos(int tid, int i) { return pos(0, tid, i >> K1, i & ((1 << K1) - 1)); }
+  __device__ static __forceinline__ int cl_pos(int tid, int i) { return tid + i * T; }
 
-  template <int K>
-  __device__ static __forceinline__ void round_fwd(uint64_t* x, int r, int tid, uint32_t B0, const uint64_t* tw,
-                                                   uint64_t q, uint64_t two_q) {
+  template <int K, class Ar>
+  __device__ static __forceinline__ void round_fwd(const Ar& A, typename Ar::T* x, int r, int tid, uint32_t B0) {
 #pragma unroll
-    for (int u = 0; u < (E >> K); ++u) sub_fwd<K>(x + u * (1 << K), tw, base(r, tid, u, B0), q, two_q);
+    for (int u = 0; u < (E >> K); ++u) sub_fwd<K>(A, x + u * (1 << K), base(r, tid, u, B0));
   }
-  template <int K>
-  __device__ static __forceinline__ void round_inv(uint64_t* x, int r, int tid, uint32_t B0, const uint64_t* tw,
-                                                   uint64_t q, uint64_t two_q) {
+  template <int K, class Ar>
+  __device__ static __forceinline__ void round_inv(const Ar& A, typename Ar::T* x, int r, int tid, uint32_t B0) {
 #pragma unroll
-    for (int u = 0; u < (E >> K); ++u) sub_inv<K>(x + u * (1 << K), tw, base(r, tid, u, B0), q, two_q);
+    for (int u = 0; u < (E >> K); ++u) sub_inv<K>(A, x + u * (1 << K), base(r, tid, u, B0));
   }
-  template <int K>
-  __device__ static __forceinline__ void to_lds(const uint64_t* x, uint64_t* lds, int r, int tid) {
+  template <int K, class V>
+  __device__ static __forceinline__ void to_lds(const V* x, V* lds, int r, int tid) {
 #pragma unroll
     for (int u = 0; u < (E >> K); ++u)
 #pragma unroll
       for (int j = 0; j < (1 << K); ++j) lds[lds_pad(pos(r, tid, u, j))] = x[u * (1 << K) + j];
   }
-  template <int K>
-  __device__ static __forceinline__ void from_lds(uint64_t* x, const uint64_t* lds, int r, int tid) {
+  template <int K, class V>
+  __device__ static __forceinline__ void from_lds(V* x, const V* lds, int r, int tid) {
 #pragma unroll
     for (int u = 0; u < (E >> K); ++u)
 #pragma unroll
       for (int j = 0; j < (1 << K); ++j) x[u * (1 << K) + j] = lds[lds_pad(pos(r, tid, u, j))];
   }
 
-  // Forward: x enters in the FR layout (values in [0, 4q)) and leaves in the
-  // LR layout (values in [0, 4q)). B0 = R + b. Starts with a barrier so the
-  // LDS block may be reused right after a previous call.
-  __device__ static void fwd(uint64_t* x, uint64_t* lds, int tid, uint32_t B0, const uint64_t* tw, uint64_t q,
-                             uint64_t two_q) {
-    round_fwd<K1>(x, 0, tid, B0, tw, q, two_q);
+  // Forward: x enters in FR, leaves in CL. B0 = R + b. Starts with a barrier
+  // so the LDS block may be reused right after a previous call.
+  template <class Ar>
+  __device__ static void fwd(const Ar& A, typename Ar::T* x, typename Ar::T* lds, int tid, uint32_t B0) {
+    round_fwd<K1>(A, x, 0, tid, B0);
     __syncthreads();
     to_lds<K1>(x, lds, 0, tid);
 #pragma unroll
     for (int r = 1; r < NR; ++r) {
       __syncthreads();
       from_lds<LOGE>(x, lds, r, tid);
-      round_fwd<LOGE>(x, r, tid, B0, tw, q, two_q);
-      if (r + 1 < NR) to_lds<LOGE>(x, lds, r, tid);
+      round_fwd<LOGE>(A, x, r, tid, B0);
+      to_lds<LOGE>(x, lds, r, tid);
     }
-  }
-
-  // Inverse: x enters in the LR layout (values in [0, 2q)) and leaves in the
-  // FR layout (values in [0, 2q)).
-  __device__ static void inv(uint64_t* x, uint64_t* lds, int tid, uint32_t B0, const uint64_t* tw, uint64_t q,
-                             uint64_t two_q) {
     __syncthreads();
 #pragma unroll
+    for (int i = 0; i < E; ++i) x[i] = lds[lds_pad(cl_pos(tid, i))];
+  }
+
+  // Inverse: x enters in CL, leaves in FR.
+  template <class Ar>
+  __device__ static void inv(const Ar& A, typename Ar::T* x, typename Ar::T* lds, int tid, uint32_t B0) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < E; ++i) lds[lds_pad(cl_pos(tid, i))] = x[i];
+#pragma unroll
     for (int r = NR - 1; r >= 1; --r) {
-      if (r + 1 < NR) from_lds<LOGE>(x, lds, r, tid);
-      round_inv<LOGE>(x, r, tid, B0, tw, q, two_q);
-      to_lds<LOGE>(x, lds, r, tid);
       __syncthreads();
+      from_lds<LOGE>(x, lds, r, tid);
+      round_inv<LOGE>(A, x, r, tid, B0);
+      to_lds<LOGE>(x, lds, r, tid);
     }
+    __syncthreads();
     from_lds<K1>(x, lds, 0, tid);
-    round_inv<K1>(x, 0, tid, B0, tw, q, two_q);
+    round_inv<K1>(A, x, 0, tid, B0);
   }
 };
 

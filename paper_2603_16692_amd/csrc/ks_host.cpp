@@ -8,6 +8,7 @@
 #include "ks_host.hpp"
 
 #include <algorithm>
+#include <cstring>
 
 namespace ks {
 
@@ -134,7 +135,20 @@ void build_tables(const HostParams& hp, std::vector<uint64_t>& blob, DevTables& 
   const size_t o_dn_pinv = take((size_t)ell * 2);
   const size_t o_up_hinv = take((size_t)ell * 2);
   const size_t o_dn_hinv = take((size_t)k * 2);
+  const size_t o_twf_d = take((size_t)ell * n);
+  const size_t o_twi_d = take((size_t)ell * n);
+  const size_t o_up_pre_d = take((size_t)ell);
+  const size_t o_up_mat_d = take((size_t)ell * ell);
+  const size_t o_dn_mat_d = take((size_t)k * ell * 2);
+  const size_t o_dn_pinv_d = take((size_t)ell);
   blob.assign(off, 0);
+  // balanced representative of a residue as a double (Q primes only)
+  auto bal = [](uint64_t v, uint64_t q) {
+    const double d = v <= q / 2 ? (double)v : -(double)(q - v);
+    uint64_t bits;
+    std::memcpy(&bits, &d, sizeof(bits));
+    return bits;
+  };
 
   auto put = [&](size_t o, uint64_t w, uint64_t q) {
     blob[o] = w;
@@ -152,7 +166,13 @@ void build_tables(const HostParams& hp, std::vector<uint64_t>& blob, DevTables& 
     L.ninv = inv_prime(n % q, q);
     L.ninv_s = shoup(L.ninv, q);
     L.red_s = shoup(1, q);
-    std::copy_n(reinterpret_cast<const uint64_t*>(&L), sizeof(LimbC) / 8, blob.begin() + o_limb + (size_t)t * 8);
+    L.qd = (double)q;
+    L.qinv = 1.0 / (double)q;
+    {
+      uint64_t b = bal(L.ninv, q);
+      std::memcpy(&L.ninv_d, &b, sizeof(b));
+    }
+    std::copy_n(reinterpret_cast<const uint64_t*>(&L), sizeof(LimbC) / 8, blob.begin() + o_limb + (size_t)t * (sizeof(LimbC) / 8));
 
     // powers psi^e and psi^-e for e < N, then the bit-reversed tables
     std::vector<uint64_t> pw(n), ipw(n);
@@ -166,6 +186,10 @@ void build_tables(const HostParams& hp, std::vector<uint64_t>& blob, DevTables& 
       const uint32_t r = bitrev((uint32_t)i, hp.log_n);
       put(o_twf + ((size_t)t * n + i) * 2, pw[r], q);
       put(o_twi + ((size_t)t * n + i) * 2, ipw[r], q);
+      if (t < ell) {
+        blob[o_twf_d + (size_t)t * n + i] = bal(pw[r], q);
+        blob[o_twi_d + (size_t)t * n + i] = bal(ipw[r], q);
+      }
     }
   }
 
@@ -179,13 +203,16 @@ void build_tables(const HostParams& hp, std::vector<uint64_t>& blob, DevTables& 
       if (i2 != i) hat = host_mulmod(hat, hp.mod[i2] % qi, qi);
     const uint64_t hinv = inv_prime(hat, qi);
     put(o_up_hinv + (size_t)i * 2, hinv, qi);
-    put(o_up_pre + (size_t)i * 2, host_mulmod(hinv, inv_prime(n % qi, qi), qi), qi);
+    const uint64_t pre = host_mulmod(hinv, inv_prime(n % qi, qi), qi);
+    put(o_up_pre + (size_t)i * 2, pre, qi);
+    blob[o_up_pre_d + i] = bal(pre, qi);
     for (int t = 0; t < nl; ++t) {
       const uint64_t m = hp.mod[t];
       uint64_t v = 1;
       for (int i2 = lo; i2 < hi; ++i2)
         if (i2 != i) v = host_mulmod(v, hp.mod[i2] % m, m);
       put(o_up_mat + ((size_t)i * nl + t) * 2, v, m);
+      if (t < ell) blob[o_up_mat_d + (size_t)i * ell + t] = bal(v, m);
     }
   }
 
@@ -204,13 +231,17 @@ void build_tables(const HostParams& hp, std::vector<uint64_t>& blob, DevTables& 
       for (int m2 = 0; m2 < k; ++m2)
         if (m2 != m) v = host_mulmod(v, hp.mod[ell + m2] % qi, qi);
       put(o_dn_mat + ((size_t)m * ell + i) * 2, v, qi);
+      blob[o_dn_mat_d + ((size_t)m * ell + i) * 2] = bal(host_mulmod(v, (1ull << 30) % qi, qi), qi);
+      blob[o_dn_mat_d + ((size_t)m * ell + i) * 2 + 1] = bal(v, qi);
     }
   }
   for (int i = 0; i < ell; ++i) {
     const uint64_t qi = hp.mod[i];
     uint64_t pmod = 1;
     for (int m = 0; m < k; ++m) pmod = host_mulmod(pmod, hp.mod[ell + m] % qi, qi);
-    put(o_dn_pinv + (size_t)i * 2, inv_prime(pmod, qi), qi);
+    const uint64_t pinv = inv_prime(pmod, qi);
+    put(o_dn_pinv + (size_t)i * 2, pinv, qi);
+    blob[o_dn_pinv_d + i] = bal(pinv, qi);
   }
 
   tb.log_n = hp.log_n;
@@ -230,6 +261,13 @@ void build_tables(const HostParams& hp, std::vector<uint64_t>& blob, DevTables& 
   tb.dn_pinv = at(o_dn_pinv);
   tb.up_hinv = at(o_up_hinv);
   tb.dn_hinv = at(o_dn_hinv);
+  auto atd = [](size_t o) { return reinterpret_cast<const double*>(o * sizeof(uint64_t)); };
+  tb.twf_d = atd(o_twf_d);
+  tb.twi_d = atd(o_twi_d);
+  tb.up_pre_d = atd(o_up_pre_d);
+  tb.up_mat_d = atd(o_up_mat_d);
+  tb.dn_mat_d = atd(o_dn_mat_d);
+  tb.dn_pinv_d = atd(o_dn_pinv_d);
 }
 
 }  // namespace ks

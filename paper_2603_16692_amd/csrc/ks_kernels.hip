@@ -5,11 +5,14 @@
 //     the first log R stages of the forward transform (or the last log R of the
 //     inverse) in registers; consecutive threads touch consecutive addresses;
 //   * a block pass: a workgroup owns M consecutive coefficients and runs the
-//     remaining log M stages through LDS (BlockNtt).
+//     remaining log M stages through LDS (BlockNtt), with coalesced global
+//     loads and stores at both ends.
 // ModUp's BConv sits between the inverse column pass and the forward column
-// pass of the new limbs (same columns), KeyMult sits after the forward block
-// pass, and ModDown repeats the pattern. Every kernel keeps the element ranges
-// stated next to it; canonical residues leave the library.
+// pass of the new limbs (same columns, all in registers), KeyMult follows the
+// forward block pass, and ModDown repeats the pattern. Q limbs (q < 2^50) run
+// on FP64 arithmetic (ArF), P limbs (p < 2^60) on 64-bit integers (ArI); the
+// choice is made per workgroup, since a workgroup works on a single limb.
+// Every kernel states the ranges of the values it reads and writes.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -23,133 +26,223 @@ namespace {
 
 constexpr int TC = 64;  // threads of a column-pass workgroup
 
-__device__ __forceinline__ size_t lane_col(int M) { return (size_t)blockIdx.x * TC + threadIdx.x; }
+__device__ __forceinline__ size_t lane_col() { return (size_t)blockIdx.x * TC + threadIdx.x; }
+
+__device__ __forceinline__ ArF arf(const DevTables& tb, const LimbC& L, int limb, bool inverse) {
+  const size_t N = (size_t)1 << tb.log_n;
+  return ArF{L.qd, L.qinv, (inverse ? tb.twi_d : tb.twf_d) + (size_t)limb * N};
+}
+__device__ __forceinline__ ArI ari(const DevTables& tb, const LimbC& L, int limb, bool inverse) {
+  const size_t N = (size_t)1 << tb.log_n;
+  return ArI{L.q, L.two_q, (inverse ? tb.twi : tb.twf) + (size_t)limb * N * 2};
+}
+
+// Canonical double in [0, q) -> uint64.
+__device__ __forceinline__ uint64_t d2u(double v) {
+  return (uint64_t)__double_as_longlong(v + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
+}
 
 // ------------------------------------------------------- standalone passes
 
 // Column pass of ks_ntt / ks_intt on x [items][nlimbs][N] (limb r uses prime
-// first + r). Forward: [0, q) or [0, 4q) in -> [0, 4q) out. Inverse: [0, 2q) in
-// -> canonical out (includes N^-1).
+// first + r). Q limbs: canonical in and out. P limbs: forward [0, 4q) in and
+// out; inverse [0, 2q) in, canonical out. The inverse includes N^-1.
 template <int LOGR, bool INV>
 __global__ __launch_bounds__(TC) void k_cols(DevTables tb, uint64_t* x, int first, int nlimbs, int log_m) {
   constexpr int R = 1 << LOGR;
   const int M = 1 << log_m;
-  const size_t c = lane_col(M);
+  const size_t c = lane_col();
   if (c >= (size_t)M) return;
   const int limb = first + blockIdx.y;
   const LimbC L = tb.limb[limb];
   const size_t N = (size_t)M * R;
   uint64_t* a = x + ((size_t)blockIdx.z * nlimbs + blockIdx.y) * N;
-  uint64_t v[R];
+  if (limb < tb.ell) {
+    const ArF A = arf(tb, L, limb, INV);
+    double v[R];
 #pragma unroll
-  for (int i = 0; i < R; ++i) v[i] = a[c + (size_t)i * M];
-  if (!INV) {
-    sub_fwd<LOGR>(v, tb.twf + (size_t)limb * N * 2, 1u, L.q, L.two_q);
+    for (int i = 0; i < R; ++i) v[i] = u2d(a[c + (size_t)i * M]);
+    if (!INV) {
+      sub_fwd<LOGR>(A, v, 1u);
+    } else {
+      sub_inv<LOGR>(A, v, 1u);
+#pragma unroll
+      for (int i = 0; i < R; ++i) v[i] = f_mul(v[i], L.ninv_d, L.qd, L.qinv);
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) a[c + (size_t)i * M] = f_canon(v[i], L.qd, L.qinv);
   } else {
-    sub_inv<LOGR>(v, tb.twi + (size_t)limb * N * 2, 1u, L.q, L.two_q);
+    const ArI A = ari(tb, L, limb, INV);
+    uint64_t v[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i) v[i] = reduce2(mul_shoup(v[i], L.ninv, L.ninv_s, L.q), L.q);
+    for (int i = 0; i < R; ++i) v[i] = a[c + (size_t)i * M];
+    if (!INV) {
+      sub_fwd<LOGR>(A, v, 1u);
+    } else {
+      sub_inv<LOGR>(A, v, 1u);
+#pragma unroll
+      for (int i = 0; i < R; ++i) v[i] = reduce2(mul_shoup(v[i], L.ninv, L.ninv_s, L.q), L.q);
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) a[c + (size_t)i * M] = v[i];
   }
-#pragma unroll
-  for (int i = 0; i < R; ++i) a[c + (size_t)i * M] = v[i];
 }
 
-// Block pass of ks_ntt / ks_intt: block b of limb (blockIdx.y) of item
-// (blockIdx.z). Forward leaves canonical values; inverse takes canonical
-// values and leaves [0, 2q) (the column pass follows), or canonical values
-// times N^-1 when `scale` is set (a one-pass ks_intt).
+// Block pass of ks_ntt / ks_intt (and of d at the start of ModUp): block b of
+// limb first + blockIdx.y of item blockIdx.z, src -> dst (may alias).
+// Forward: Q canonical in; P [0, 4q) in; canonical out. Inverse: canonical in;
+// out Q canonical, P [0, 2q); times N^-1 (canonical) when `scale` is set.
 template <int LOGM, int LOGE, bool INV>
 __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_blocks(DevTables tb, const uint64_t* src, uint64_t* dst,
-                                                                    int first, int nlimbs, int scale) {
+                                                                 int first, int nlimbs, int scale) {
   using B = BlockNtt<LOGM, LOGE>;
   extern __shared__ uint64_t lds[];
   const int tid = threadIdx.x, b = blockIdx.x;
   const int limb = first + blockIdx.y;
   const LimbC L = tb.limb[limb];
   const size_t N = (size_t)1 << tb.log_n;
-  const int R = (int)(N >> LOGM);
+  const uint32_t B0 = (uint32_t)(N >> LOGM) + b;
   const size_t off = ((size_t)blockIdx.z * nlimbs + blockIdx.y) * N + (size_t)b * B::M;
   const uint64_t* s = src + off;
   uint64_t* d = dst + off;
-  uint64_t v[B::E];
-  if (!INV) {
+  if (limb < tb.ell) {
+    const ArF A = arf(tb, L, limb, INV);
+    double* ld = reinterpret_cast<double*>(lds);
+    double v[B::E];
+    if (!INV) {
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = s[B::fr_pos(tid, i)];
-    B::fwd(v, lds, tid, (uint32_t)(R + b), tb.twf + (size_t)limb * N * 2, L.q, L.two_q);
+      for (int i = 0; i < B::E; ++i) v[i] = u2d(s[B::fr_pos(tid, i)]);
+      B::fwd(A, v, ld, tid, B0);
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) d[B::lr_pos(tid, i)] = reduce4(v[i], L.q, L.two_q);
-  } else {
+      for (int i = 0; i < B::E; ++i) d[B::cl_pos(tid, i)] = f_canon(v[i], L.qd, L.qinv);
+    } else {
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) v[i] = s[B::lr_pos(tid, i)];
-    B::inv(v, lds, tid, (uint32_t)(R + b), tb.twi + (size_t)limb * N * 2, L.q, L.two_q);
-    if (scale) {  // the whole transform was this block: apply N^-1 here
+      for (int i = 0; i < B::E; ++i) v[i] = u2d(s[B::cl_pos(tid, i)]);
+      B::inv(A, v, ld, tid, B0);
+      if (scale) {
 #pragma unroll
-      for (int i = 0; i < B::E; ++i) v[i] = reduce2(mul_shoup(v[i], L.ninv, L.ninv_s, L.q), L.q);
+        for (int i = 0; i < B::E; ++i) v[i] = f_mul(v[i], L.ninv_d, L.qd, L.qinv);
+      }
+#pragma unroll
+      for (int i = 0; i < B::E; ++i) d[B::fr_pos(tid, i)] = f_canon(v[i], L.qd, L.qinv);
     }
+  } else {
+    const ArI A = ari(tb, L, limb, INV);
+    uint64_t v[B::E];
+    if (!INV) {
 #pragma unroll
-    for (int i = 0; i < B::E; ++i) d[B::fr_pos(tid, i)] = v[i];
+      for (int i = 0; i < B::E; ++i) v[i] = s[B::fr_pos(tid, i)];
+      B::fwd(A, v, lds, tid, B0);
+#pragma unroll
+      for (int i = 0; i < B::E; ++i) d[B::cl_pos(tid, i)] = reduce4(v[i], L.q, L.two_q);
+    } else {
+#pragma unroll
+      for (int i = 0; i < B::E; ++i) v[i] = s[B::cl_pos(tid, i)];
+      B::inv(A, v, lds, tid, B0);
+      if (scale) {
+#pragma unroll
+        for (int i = 0; i < B::E; ++i) v[i] = reduce2(mul_shoup(v[i], L.ninv, L.ninv_s, L.q), L.q);
+      }
+#pragma unroll
+      for (int i = 0; i < B::E; ++i) d[B::fr_pos(tid, i)] = v[i];
+    }
   }
 }
 
 // ------------------------------------------------------------ ModUp (K2)
 
-// For digits j0 + blockIdx.y and columns c: INTT column pass of the digit's
-// limbs of t1 (block-pass output of d, [0, 2q)), times N^-1 [(D_j/q_i)^-1]
-// (canonical y_i, staged in LDS), BConv to every target limb t in
-// [tgt0, tgt1) outside D_j, forward column pass, store to ext1 slot.
-// ext1 [items][slots][nl][N]; slot = (slot_stride ? j : 0).
+// A column-pass workgroup: 4 waves over the same 64 columns (the 64 lanes).
+// Sources are converted once into LDS (wave w takes sources w, w+4, ...);
+// after a barrier the waves split the target limbs the same way, so the
+// registers a thread needs do not grow with the number of sources.
+constexpr int CW = 4;               // waves per column workgroup
+constexpr int CT = CW * TC;         // threads per column workgroup
+
+// Digit j = j0 + blockIdx.y of item blockIdx.z, columns blockIdx.x*64 + lane:
+// inverse column pass of the digit's limbs of t1 (the block-pass output of d,
+// canonical), times N^-1 [(D_j/q_i)^-1]_{q_i}, giving canonical y_i (in LDS,
+// [alpha][R][64] doubles); then for every target limb t in [tgt0, tgt1)
+// outside D_j: z_t = sum_i y_i [D_j/q_i]_t, forward column pass, store into
+// ext1 [items][nslots][nl][N] at slot (slot_stride ? j : 0). Q targets are
+// stored canonical, P targets in [0, 4q).
 template <int LOGR>
-__global__ __launch_bounds__(TC) void k_modup_cols(DevTables tb, const uint64_t* t1, uint64_t* ext1, int j0,
+__global__ __launch_bounds__(CT) void k_modup_cols(DevTables tb, const uint64_t* t1, uint64_t* ext1, int j0,
                                                    int nslots, int slot_stride, int tgt0, int tgt1, int log_m) {
   constexpr int R = 1 << LOGR;
-  extern __shared__ uint64_t ylds[];  // [alpha][R][TC]
+  extern __shared__ double ys[];
   const int M = 1 << log_m;
   const size_t N = (size_t)M * R;
-  const size_t c = lane_col(M);
+  const int lane = threadIdx.x & (TC - 1), wv = threadIdx.x / TC;
+  const size_t c = (size_t)blockIdx.x * TC + lane;
   const bool live = c < (size_t)M;
   const int j = j0 + blockIdx.y;
   const int item = blockIdx.z;
+  const int ell = tb.ell, nl = tb.nl;
   const int lo = j * tb.alpha;
-  const int hi = min(lo + tb.alpha, tb.ell);
-  const int tid = threadIdx.x;
+  const int na = min(lo + tb.alpha, ell) - lo;
   if (live) {
-    for (int i = lo; i < hi; ++i) {
+    for (int s = wv; s < na; s += CW) {
+      const int i = lo + s;
       const LimbC L = tb.limb[i];
-      const uint64_t* a = t1 + ((size_t)item * tb.ell + i) * N;
-      uint64_t v[R];
+      const uint64_t* a = t1 + ((size_t)item * ell + i) * N;
+      double v[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[r] = a[c + (size_t)r * M];
-      sub_inv<LOGR>(v, tb.twi + (size_t)i * N * 2, 1u, L.q, L.two_q);
-      const uint64_t w = tb.up_pre[2 * i], ws = tb.up_pre[2 * i + 1];
+      for (int r = 0; r < R; ++r) v[r] = u2d(a[c + (size_t)r * M]);
+      sub_inv<LOGR>(arf(tb, L, i, true), v, 1u);
+      const double w = tb.up_pre_d[i];
 #pragma unroll
-      for (int r = 0; r < R; ++r) ylds[((i - lo) * R + r) * TC + tid] = reduce2(mul_shoup(v[r], w, ws, L.q), L.q);
+      for (int r = 0; r < R; ++r) ys[(s * R + r) * TC + lane] = f_canon_d(f_mul(v[r], w, L.qd, L.qinv), L.qd, L.qinv);
     }
   }
+  __syncthreads();
   if (!live) return;
   const int slot = slot_stride ? j : 0;
-  uint64_t* e = ext1 + ((size_t)item * nslots + slot) * (size_t)tb.nl * N;
+  uint64_t* e = ext1 + ((size_t)item * nslots + slot) * (size_t)nl * N;
+  int u = 0;  // index of the target among those outside D_j
   for (int t = tgt0; t < tgt1; ++t) {
-    if (t >= lo && t < hi) continue;
+    if (t >= lo && t < lo + na) continue;
+    if ((u++ % CW) != wv) continue;
     const LimbC L = tb.limb[t];
-    uint64_t z[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) z[r] = 0;
-    for (int i = lo; i < hi; ++i) {
-      const uint64_t w = tb.up_mat[2 * ((size_t)i * tb.nl + t)], ws = tb.up_mat[2 * ((size_t)i * tb.nl + t) + 1];
-#pragma unroll
-      for (int r = 0; r < R; ++r) z[r] += reduce2(mul_shoup(ylds[((i - lo) * R + r) * TC + tid], w, ws, L.q), L.q);
-      if (((i - lo) & 7) == 7) {  // keep the sum below 8q < 2^63
-#pragma unroll
-        for (int r = 0; r < R; ++r) z[r] = reduce2(mul_shoup(z[r], 1, L.red_s, L.q), L.q);
-      }
-    }
-    // the sum holds at most 8 values below q: fold with Shoup by 1
-#pragma unroll
-    for (int r = 0; r < R; ++r) z[r] = reduce2(mul_shoup(z[r], 1, L.red_s, L.q), L.q);
-    sub_fwd<LOGR>(z, tb.twf + (size_t)t * N * 2, 1u, L.q, L.two_q);
     uint64_t* o = e + (size_t)t * N;
+    if (t < ell) {
+      // |y * c| <= 2^50 * 2^49: each product is within 0.875q; fold every 8
+      double z[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) o[c + (size_t)r * M] = z[r];
+      for (int r = 0; r < R; ++r) z[r] = 0.0;
+      for (int s = 0; s < na; ++s) {
+        const double cst = tb.up_mat_d[(size_t)(lo + s) * ell + t];
+#pragma unroll
+        for (int r = 0; r < R; ++r) z[r] += f_mul(ys[(s * R + r) * TC + lane], cst, L.qd, L.qinv);
+        if ((s & 7) == 7) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) z[r] = f_red(z[r], L.qd, L.qinv);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) z[r] = f_red(z[r], L.qd, L.qinv);
+      sub_fwd<LOGR>(arf(tb, L, t, false), z, 1u);
+#pragma unroll
+      for (int r = 0; r < R; ++r) o[c + (size_t)r * M] = f_canon(z[r], L.qd, L.qinv);
+    } else {
+      uint64_t z[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) z[r] = 0;
+      for (int s = 0; s < na; ++s) {
+        const size_t ci = 2 * ((size_t)(lo + s) * nl + t);
+        const uint64_t w = tb.up_mat[ci], ws = tb.up_mat[ci + 1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) z[r] += reduce2(mul_shoup(d2u(ys[(s * R + r) * TC + lane]), w, ws, L.q), L.q);
+        if ((s & 7) == 7) {  // keep the sum below 8q < 2^63
+#pragma unroll
+          for (int r = 0; r < R; ++r) z[r] = reduce2(mul_shoup(z[r], 1, L.red_s, L.q), L.q);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) z[r] = reduce2(mul_shoup(z[r], 1, L.red_s, L.q), L.q);
+      sub_fwd<LOGR>(ari(tb, L, t, false), z, 1u);
+#pragma unroll
+      for (int r = 0; r < R; ++r) o[c + (size_t)r * M] = z[r];
+    }
   }
 }
 
@@ -157,10 +250,9 @@ __global__ __launch_bounds__(TC) void k_modup_cols(DevTables tb, const uint64_t*
 
 // Block b of target limb t = tgt0 + blockIdx.y of item blockIdx.z: for every
 // digit j in [j0, j1): ext_j = (t in D_j) ? d : forward block pass of ext1;
-// s_c += ext_j * evk[j][c] (Montgomery). Then v_c = s_c * R^2 (canonical),
-// plus the previous acc if `accumulate`. With `finalize` and t a P limb, the
-// inverse block pass of ModDown runs on v_c (result in [0, 2q), FR layout);
-// otherwise v_c is stored canonical (LR layout).
+// s_c += ext_j * evk[j][c]. Then v_c = s_c (+ the previous acc if
+// `accumulate`), stored canonical. With `finalize` and t a P limb, the inverse
+// block pass of ModDown runs on v_c and leaves [0, 2q) in acc.
 template <int LOGM, int LOGE>
 __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_keymult_blocks(
     DevTables tb, const uint64_t* d, const uint64_t* ext1, const uint64_t* evk, uint64_t* acc, int j0, int j1,
@@ -172,39 +264,82 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_keymult_blocks(
   const int item = blockIdx.z;
   const LimbC L = tb.limb[t];
   const size_t N = (size_t)1 << tb.log_n;
-  const int R = (int)(N >> LOGM);
+  const uint32_t B0 = (uint32_t)(N >> LOGM) + b;
   const int nl = tb.nl;
   const size_t boff = (size_t)b * B::M;
+  uint64_t* a0 = acc + (((size_t)item * 2 + 0) * nl + t) * N + boff;
+  uint64_t* a1 = acc + (((size_t)item * 2 + 1) * nl + t) * N + boff;
+  if (t < tb.ell) {
+    const ArF A = arf(tb, L, t, false);
+    double* ld = reinterpret_cast<double*>(lds);
+    double s0[B::E], s1[B::E], v[B::E];
+#pragma unroll
+    for (int i = 0; i < B::E; ++i) s0[i] = s1[i] = 0.0;
+    for (int j = j0; j < j1; ++j) {
+      const int lo = j * tb.alpha;
+      if (t >= lo && t < lo + tb.alpha) {
+        const uint64_t* src = d + ((size_t)item * tb.ell + t) * N + boff;
+#pragma unroll
+        for (int i = 0; i < B::E; ++i) v[i] = u2d(src[B::cl_pos(tid, i)]);
+      } else {
+        const int slot = slot_stride ? j : 0;
+        const uint64_t* src = ext1 + (((size_t)item * nslots + slot) * nl + t) * N + boff;
+#pragma unroll
+        for (int i = 0; i < B::E; ++i) v[i] = u2d(src[B::fr_pos(tid, i)]);
+        B::fwd(A, v, ld, tid, B0);
+      }
+      const uint64_t* k0 = evk + (((size_t)j * 2 + 0) * nl + t) * N + boff;
+      const uint64_t* k1 = evk + (((size_t)j * 2 + 1) * nl + t) * N + boff;
+      // |v| <= 2q, key < q: each product is within 1.25q; fold every 4 digits
+#pragma unroll
+      for (int i = 0; i < B::E; ++i) {
+        const int x = B::cl_pos(tid, i);
+        s0[i] += f_mul(v[i], u2d(k0[x]), L.qd, L.qinv);
+        s1[i] += f_mul(v[i], u2d(k1[x]), L.qd, L.qinv);
+      }
+      if (((j - j0) & 3) == 3) {
+#pragma unroll
+        for (int i = 0; i < B::E; ++i) {
+          s0[i] = f_red(s0[i], L.qd, L.qinv);
+          s1[i] = f_red(s1[i], L.qd, L.qinv);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < B::E; ++i) {
+      const int x = B::cl_pos(tid, i);
+      double u0 = f_red(s0[i], L.qd, L.qinv), u1 = f_red(s1[i], L.qd, L.qinv);
+      if (accumulate) {
+        u0 += u2d(a0[x]);
+        u1 += u2d(a1[x]);
+      }
+      a0[x] = f_canon(u0, L.qd, L.qinv);
+      a1[x] = f_canon(u1, L.qd, L.qinv);
+    }
+    return;
+  }
+  const ArI A = ari(tb, L, t, false);
   uint64_t s0[B::E], s1[B::E], v[B::E];
 #pragma unroll
   for (int i = 0; i < B::E; ++i) s0[i] = s1[i] = 0;
   for (int j = j0; j < j1; ++j) {
-    const int lo = j * tb.alpha, hi = min(lo + tb.alpha, tb.ell);
-    if (t >= lo && t < hi) {
-      const uint64_t* src = d + ((size_t)item * tb.ell + t) * N + boff;
+    const int slot = slot_stride ? j : 0;
+    const uint64_t* src = ext1 + (((size_t)item * nslots + slot) * nl + t) * N + boff;
 #pragma unroll
-      for (int i = 0; i < B::E; ++i) v[i] = src[B::lr_pos(tid, i)];
-    } else {
-      const int slot = slot_stride ? j : 0;
-      const uint64_t* src = ext1 + (((size_t)item * nslots + slot) * nl + t) * N + boff;
-#pragma unroll
-      for (int i = 0; i < B::E; ++i) v[i] = src[B::fr_pos(tid, i)];
-      B::fwd(v, lds, tid, (uint32_t)(R + b), tb.twf + (size_t)t * N * 2, L.q, L.two_q);
-    }
+    for (int i = 0; i < B::E; ++i) v[i] = src[B::fr_pos(tid, i)];
+    B::fwd(A, v, lds, tid, B0);
     const uint64_t* k0 = evk + (((size_t)j * 2 + 0) * nl + t) * N + boff;
     const uint64_t* k1 = evk + (((size_t)j * 2 + 1) * nl + t) * N + boff;
 #pragma unroll
     for (int i = 0; i < B::E; ++i) {
-      const int x = B::lr_pos(tid, i);
-      // running sums stay in [0, 2q): each product is in [0, 2q)
+      const int x = B::cl_pos(tid, i);
+      // running sums stay in [0, 2q): each Montgomery product is in [0, 2q)
       s0[i] += mont_mul(v[i], k0[x], L.q, L.mont_ninv);
       s0[i] = s0[i] >= L.two_q ? s0[i] - L.two_q : s0[i];
       s1[i] += mont_mul(v[i], k1[x], L.q, L.mont_ninv);
       s1[i] = s1[i] >= L.two_q ? s1[i] - L.two_q : s1[i];
     }
   }
-  uint64_t* a0 = acc + (((size_t)item * 2 + 0) * nl + t) * N + boff;
-  uint64_t* a1 = acc + (((size_t)item * 2 + 1) * nl + t) * N + boff;
 #pragma unroll
   for (int i = 0; i < B::E; ++i) {
     // s < 2q, so s * r2 < 2 q^2 < q * 2^64
@@ -214,23 +349,23 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_keymult_blocks(
   if (accumulate) {
 #pragma unroll
     for (int i = 0; i < B::E; ++i) {
-      const int x = B::lr_pos(tid, i);
+      const int x = B::cl_pos(tid, i);
       s0[i] = reduce2(s0[i] + a0[x], L.q);
       s1[i] = reduce2(s1[i] + a1[x], L.q);
     }
   }
-  if (finalize && t >= tb.ell) {
-    const uint64_t* twi = tb.twi + (size_t)t * N * 2;
-    B::inv(s0, lds, tid, (uint32_t)(R + b), twi, L.q, L.two_q);
+  if (finalize) {
+    const ArI Ai = ari(tb, L, t, true);
+    B::inv(Ai, s0, lds, tid, B0);
 #pragma unroll
     for (int i = 0; i < B::E; ++i) a0[B::fr_pos(tid, i)] = s0[i];
-    B::inv(s1, lds, tid, (uint32_t)(R + b), twi, L.q, L.two_q);
+    B::inv(Ai, s1, lds, tid, B0);
 #pragma unroll
     for (int i = 0; i < B::E; ++i) a1[B::fr_pos(tid, i)] = s1[i];
   } else {
 #pragma unroll
     for (int i = 0; i < B::E; ++i) {
-      const int x = B::lr_pos(tid, i);
+      const int x = B::cl_pos(tid, i);
       a0[x] = s0[i];
       a1[x] = s1[i];
     }
@@ -239,86 +374,100 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_keymult_blocks(
 
 // ---------------------------------------------------------- ModDown (K4)
 
-// Columns of component blockIdx.y of item blockIdx.z: INTT column pass of
-// the k P limbs (inputs: the block-pass output, [0, 2q), read from accp
-// [items][2][nl][N] at limbs ell..nl-1), times N^-1 [(P/p_m)^-1] (canonical y_m
-// in LDS), BConv to Q limbs i in [tgt0, tgt1), forward column pass, store to
-// t2 [items][2][ell][N].
+// Component blockIdx.y of item blockIdx.z, columns blockIdx.x*64 + lane:
+// inverse column pass of the k P limbs (accp [items][2][nl][N] at limbs ell..,
+// values in [0, 2q)), times N^-1 [(P/p_m)^-1]: canonical y_m < 2^60 in LDS
+// ([k][R][64] uint64). Then for Q limbs i in [tgt0, tgt1), split over the
+// waves: z_i = sum_m y_m [P/p_m]_{q_i}, computed in FP64 as
+// y_hi [2^30 P/p_m] + y_lo [P/p_m] with y_m = y_hi 2^30 + y_lo; forward column
+// pass; t2 [items][2][ell][N] canonical.
 template <int LOGR>
-__global__ __launch_bounds__(TC) void k_moddown_cols(DevTables tb, const uint64_t* accp, uint64_t* t2, int tgt0,
+__global__ __launch_bounds__(CT) void k_moddown_cols(DevTables tb, const uint64_t* accp, uint64_t* t2, int tgt0,
                                                      int tgt1, int log_m) {
   constexpr int R = 1 << LOGR;
-  extern __shared__ uint64_t ylds[];  // [k][R][TC]
+  extern __shared__ uint64_t yl[];
   const int M = 1 << log_m;
   const size_t N = (size_t)M * R;
-  const size_t c = lane_col(M);
-  if (c >= (size_t)M) return;
-  const int comp = blockIdx.y, item = blockIdx.z, tid = threadIdx.x;
-  const int ell = tb.ell, nl = tb.nl;
-  for (int m = 0; m < tb.k; ++m) {
-    const LimbC L = tb.limb[ell + m];
-    const uint64_t* a = accp + (((size_t)item * 2 + comp) * nl + ell + m) * N;
-    uint64_t v[R];
+  const int lane = threadIdx.x & (TC - 1), wv = threadIdx.x / TC;
+  const size_t c = (size_t)blockIdx.x * TC + lane;
+  const bool live = c < (size_t)M;
+  const int comp = blockIdx.y, item = blockIdx.z;
+  const int ell = tb.ell, nl = tb.nl, k = tb.k;
+  if (live) {
+    for (int m = wv; m < k; m += CW) {
+      const LimbC L = tb.limb[ell + m];
+      const uint64_t* a = accp + (((size_t)item * 2 + comp) * nl + ell + m) * N;
+      uint64_t v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = a[c + (size_t)r * M];
-    sub_inv<LOGR>(v, tb.twi + (size_t)(ell + m) * N * 2, 1u, L.q, L.two_q);
-    const uint64_t w = tb.dn_pre[2 * m], ws = tb.dn_pre[2 * m + 1];
+      for (int r = 0; r < R; ++r) v[r] = a[c + (size_t)r * M];
+      sub_inv<LOGR>(ari(tb, L, ell + m, true), v, 1u);
+      const uint64_t w = tb.dn_pre[2 * m], ws = tb.dn_pre[2 * m + 1];
 #pragma unroll
-    for (int r = 0; r < R; ++r) ylds[(m * R + r) * TC + tid] = reduce2(mul_shoup(v[r], w, ws, L.q), L.q);
+      for (int r = 0; r < R; ++r) yl[(m * R + r) * TC + lane] = reduce2(mul_shoup(v[r], w, ws, L.q), L.q);
+    }
   }
-  for (int i = tgt0; i < tgt1; ++i) {
+  __syncthreads();
+  if (!live) return;
+  for (int i = tgt0 + wv; i < tgt1; i += CW) {
     const LimbC L = tb.limb[i];
-    uint64_t z[R];
+    double z[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) z[r] = 0;
-    for (int m = 0; m < tb.k; ++m) {
-      const uint64_t w = tb.dn_mat[2 * ((size_t)m * ell + i)], ws = tb.dn_mat[2 * ((size_t)m * ell + i) + 1];
+    for (int r = 0; r < R; ++r) z[r] = 0.0;
+    for (int m = 0; m < k; ++m) {
+      const double ch = tb.dn_mat_d[2 * ((size_t)m * ell + i)];
+      const double cl = tb.dn_mat_d[2 * ((size_t)m * ell + i) + 1];
 #pragma unroll
-      for (int r = 0; r < R; ++r) z[r] += reduce2(mul_shoup(ylds[(m * R + r) * TC + tid], w, ws, L.q), L.q);
-      if ((m & 7) == 7) {
+      for (int r = 0; r < R; ++r) {
+        // |y_hi * c|, |y_lo * c| <= 2^79: each product is within q/2 + 1
+        const uint64_t yv = yl[(m * R + r) * TC + lane];
+        const double yh = (double)(uint32_t)(yv >> 30);
+        const double ylo = (double)(uint32_t)(yv & 0x3FFFFFFFull);
+        z[r] += f_mul(yh, ch, L.qd, L.qinv) + f_mul(ylo, cl, L.qd, L.qinv);
+      }
+      if ((m & 3) == 3) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) z[r] = reduce2(mul_shoup(z[r], 1, L.red_s, L.q), L.q);
+        for (int r = 0; r < R; ++r) z[r] = f_red(z[r], L.qd, L.qinv);
       }
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) z[r] = reduce2(mul_shoup(z[r], 1, L.red_s, L.q), L.q);
-    sub_fwd<LOGR>(z, tb.twf + (size_t)i * N * 2, 1u, L.q, L.two_q);
+    for (int r = 0; r < R; ++r) z[r] = f_red(z[r], L.qd, L.qinv);
+    sub_fwd<LOGR>(arf(tb, L, i, false), z, 1u);
     uint64_t* o = t2 + (((size_t)item * 2 + comp) * ell + i) * N;
 #pragma unroll
-    for (int r = 0; r < R; ++r) o[c + (size_t)r * M] = z[r];
+    for (int r = 0; r < R; ++r) o[c + (size_t)r * M] = f_canon(z[r], L.qd, L.qinv);
   }
 }
 
 // ---------------------------------------------------------- ModDown (K5)
 
-// Block b of Q limb i = tgt0 + blockIdx.y, component/item blockIdx.z = item*2+c:
-// forward block pass of t2, then out = (acc_Q - v) * P^-1 (canonical).
+// Block b of Q limb i = tgt0 + blockIdx.y, item/component blockIdx.z = item*2+c:
+// forward block pass of t2 (canonical), then out = (acc_Q - v) * P^-1 (canonical).
 template <int LOGM, int LOGE>
 __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_moddown_blocks(DevTables tb, const uint64_t* t2,
-                                                                            const uint64_t* acc, uint64_t* out,
-                                                                            int tgt0) {
+                                                                         const uint64_t* acc, uint64_t* out,
+                                                                         int tgt0) {
   using B = BlockNtt<LOGM, LOGE>;
   extern __shared__ uint64_t lds[];
   const int tid = threadIdx.x, b = blockIdx.x;
   const int i = tgt0 + blockIdx.y;
-  const int ic = blockIdx.z;  // item * 2 + component
+  const int ic = blockIdx.z;
   const LimbC L = tb.limb[i];
   const size_t N = (size_t)1 << tb.log_n;
-  const int R = (int)(N >> LOGM);
+  const uint32_t B0 = (uint32_t)(N >> LOGM) + b;
   const size_t boff = (size_t)b * B::M;
   const uint64_t* src = t2 + ((size_t)ic * tb.ell + i) * N + boff;
-  uint64_t v[B::E];
+  double v[B::E];
 #pragma unroll
-  for (int e = 0; e < B::E; ++e) v[e] = src[B::fr_pos(tid, e)];
-  B::fwd(v, lds, tid, (uint32_t)(R + b), tb.twf + (size_t)i * N * 2, L.q, L.two_q);
+  for (int e = 0; e < B::E; ++e) v[e] = u2d(src[B::fr_pos(tid, e)]);
+  B::fwd(arf(tb, L, i, false), v, reinterpret_cast<double*>(lds), tid, B0);
   const uint64_t* a = acc + ((size_t)ic * tb.nl + i) * N + boff;
   uint64_t* o = out + ((size_t)ic * tb.ell + i) * N + boff;
-  const uint64_t w = tb.dn_pinv[2 * i], ws = tb.dn_pinv[2 * i + 1];
-  const uint64_t four_q = 2 * L.two_q;
+  const double pinv = tb.dn_pinv_d[i];
 #pragma unroll
   for (int e = 0; e < B::E; ++e) {
-    const int x = B::lr_pos(tid, e);
-    o[x] = reduce2(mul_shoup(a[x] + four_q - v[e], w, ws, L.q), L.q);
+    const int x = B::cl_pos(tid, e);
+    // |acc - v| <= 2.4q, |P^-1| <= q/2
+    o[x] = f_canon(f_mul(u2d(a[x]) - v[e], pinv, L.qd, L.qinv), L.qd, L.qinv);
   }
 }
 
@@ -332,18 +481,27 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_ext_blocks(DevTables t
   const int tid = threadIdx.x, b = blockIdx.x;
   const int t = blockIdx.y;
   const int j = blockIdx.z % tb.ndig;
-  const int lo = j * tb.alpha, hi = min(lo + tb.alpha, tb.ell);
-  if (t >= lo && t < hi) return;  // uniform over the workgroup
+  const int lo = j * tb.alpha;
+  if (t >= lo && t < lo + tb.alpha && t < tb.ell) return;  // uniform over the workgroup
   const LimbC L = tb.limb[t];
   const size_t N = (size_t)1 << tb.log_n;
-  const int R = (int)(N >> LOGM);
+  const uint32_t B0 = (uint32_t)(N >> LOGM) + b;
   uint64_t* a = ext + ((size_t)blockIdx.z * tb.nl + t) * N + (size_t)b * B::M;
-  uint64_t v[B::E];
+  if (t < tb.ell) {
+    double v[B::E];
 #pragma unroll
-  for (int e = 0; e < B::E; ++e) v[e] = a[B::fr_pos(tid, e)];
-  B::fwd(v, lds, tid, (uint32_t)(R + b), tb.twf + (size_t)t * N * 2, L.q, L.two_q);
+    for (int e = 0; e < B::E; ++e) v[e] = u2d(a[B::fr_pos(tid, e)]);
+    B::fwd(arf(tb, L, t, false), v, reinterpret_cast<double*>(lds), tid, B0);
 #pragma unroll
-  for (int e = 0; e < B::E; ++e) a[B::lr_pos(tid, e)] = reduce4(v[e], L.q, L.two_q);
+    for (int e = 0; e < B::E; ++e) a[B::cl_pos(tid, e)] = f_canon(v[e], L.qd, L.qinv);
+  } else {
+    uint64_t v[B::E];
+#pragma unroll
+    for (int e = 0; e < B::E; ++e) v[e] = a[B::fr_pos(tid, e)];
+    B::fwd(ari(tb, L, t, false), v, lds, tid, B0);
+#pragma unroll
+    for (int e = 0; e < B::E; ++e) a[B::cl_pos(tid, e)] = reduce4(v[e], L.q, L.two_q);
+  }
 }
 
 // ext[item][j][t] = d[item][t] for t in D_j.
@@ -357,7 +515,7 @@ __global__ void k_copy_digits(DevTables tb, const uint64_t* d, uint64_t* ext) {
 }
 
 // ks_bconv: coefficient-form conversion of one source set, one thread per
-// coefficient. src [items][ns][N], dst [items][nd][N].
+// coefficient, integer arithmetic. src [items][ns][N], dst [items][nd][N].
 __global__ void k_bconv(DevTables tb, const uint64_t* src, uint64_t* dst, int set) {
   const size_t N = (size_t)1 << tb.log_n;
   const size_t x = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -384,21 +542,14 @@ __global__ void k_bconv(DevTables tb, const uint64_t* src, uint64_t* dst, int se
     const uint64_t* hinv = set < 0 ? tb.dn_hinv + 2 * s : tb.up_hinv + 2 * i;
     const uint64_t xi = src[((size_t)item * ns + s) * N + x];
     const uint64_t y = reduce2(mul_shoup(xi, hinv[0], hinv[1], S.q), S.q);
-    uint64_t cw, cws;
-    if (set < 0) {
-      cw = tb.dn_mat[2 * ((size_t)s * tb.ell + t)];
-      cws = tb.dn_mat[2 * ((size_t)s * tb.ell + t) + 1];
-    } else {
-      cw = tb.up_mat[2 * ((size_t)i * tb.nl + t)];
-      cws = tb.up_mat[2 * ((size_t)i * tb.nl + t) + 1];
-    }
-    z += reduce2(mul_shoup(y, cw, cws, L.q), L.q);
+    const uint64_t* cst = set < 0 ? tb.dn_mat + 2 * ((size_t)s * tb.ell + t) : tb.up_mat + 2 * ((size_t)i * tb.nl + t);
+    z += reduce2(mul_shoup(y, cst[0], cst[1], L.q), L.q);
     if ((s & 7) == 7) z = reduce2(mul_shoup(z, 1, L.red_s, L.q), L.q);
   }
   dst[((size_t)item * nd + u) * N + x] = reduce2(mul_shoup(z, 1, L.red_s, L.q), L.q);
 }
 
-// ks_keymult: element-wise over acc [items][2][nl][N].
+// ks_keymult: element-wise over acc [items][2][nl][N], integer arithmetic.
 __global__ void k_keymult(DevTables tb, const uint64_t* ext, const uint64_t* evk, uint64_t* acc) {
   const size_t N = (size_t)1 << tb.log_n;
   const size_t x = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -414,11 +565,11 @@ __global__ void k_keymult(DevTables tb, const uint64_t* ext, const uint64_t* evk
   acc[(((size_t)item * 2 + c) * tb.nl + t) * N + x] = reduce2(mont_mul(s, L.r2, L.q, L.mont_ninv), L.q);
 }
 
-// ks_moddown, first step: copy the P limbs of acc into the work buffer and
-// run the inverse block pass there (the caller's acc stays untouched).
+// ks_moddown, first step: inverse block pass of the P limbs of acc
+// (canonical) into the work buffer accp (same layout), values in [0, 2q).
 template <int LOGM, int LOGE>
 __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_pblocks_inv(DevTables tb, const uint64_t* acc,
-                                                                         uint64_t* accp) {
+                                                                      uint64_t* accp) {
   using B = BlockNtt<LOGM, LOGE>;
   extern __shared__ uint64_t lds[];
   const int tid = threadIdx.x, b = blockIdx.x;
@@ -426,12 +577,12 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_pblocks_inv(DevTables 
   const int ic = blockIdx.z;
   const LimbC L = tb.limb[t];
   const size_t N = (size_t)1 << tb.log_n;
-  const int R = (int)(N >> LOGM);
+  const uint32_t B0 = (uint32_t)(N >> LOGM) + b;
   const size_t off = ((size_t)ic * tb.nl + t) * N + (size_t)b * B::M;
   uint64_t v[B::E];
 #pragma unroll
-  for (int e = 0; e < B::E; ++e) v[e] = acc[off + B::lr_pos(tid, e)];
-  B::inv(v, lds, tid, (uint32_t)(R + b), tb.twi + (size_t)t * N * 2, L.q, L.two_q);
+  for (int e = 0; e < B::E; ++e) v[e] = acc[off + B::cl_pos(tid, e)];
+  B::inv(ari(tb, L, t, true), v, lds, tid, B0);
 #pragma unroll
   for (int e = 0; e < B::E; ++e) accp[off + B::fr_pos(tid, e)] = v[e];
 }
@@ -446,6 +597,7 @@ hipError_t by_logr(int log_r, A... a) {
     case 2: return F<2>::run(a...);
     case 3: return F<3>::run(a...);
     case 4: return F<4>::run(a...);
+    case 5: return F<5>::run(a...);
     default: return hipErrorInvalidValue;
   }
 }
@@ -464,15 +616,34 @@ hipError_t by_logm(int log_m, A... a) {
   }
 }
 
-dim3 col_grid(int log_m, int y, int z) { return dim3((unsigned)(((1 << log_m) + TC - 1) / TC), (unsigned)y, (unsigned)z); }
+// KeyMult keeps two accumulators per element across the digits, so its block
+// pass runs with 8 elements per thread below M = 2^13 (16 from there on, where 8
+// would need more than 128 registers at 1024 threads).
+constexpr int loge_k3(int logm) { return logm >= 13 ? 4 : (logm >= 6 ? 3 : (logm >= 4 ? 2 : 1)); }
+
+template <template <int, int> class F, typename... A>
+hipError_t by_logm_k3(int log_m, A... a) {
+  switch (log_m) {
+#define KS_CASE(m) \
+  case m: return F<m, loge_k3(m)>::run(a...);
+    KS_CASE(3) KS_CASE(4) KS_CASE(5) KS_CASE(6) KS_CASE(7) KS_CASE(8) KS_CASE(9) KS_CASE(10) KS_CASE(11)
+    KS_CASE(12) KS_CASE(13) KS_CASE(14)
+#undef KS_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+dim3 col_grid(int log_m, int y, int z) {
+  return dim3((unsigned)(((1 << log_m) + TC - 1) / TC), (unsigned)y, (unsigned)z);
+}
 
 template <int LOGM, int LOGE>
 size_t block_lds() {
   return sizeof(uint64_t) * BlockNtt<LOGM, LOGE>::LDS_WORDS;
 }
 
-// Allows a kernel to take up to the whole 160 KB of LDS as dynamic shared
-// memory (done once per kernel instantiation).
+// Lets a kernel take up to the whole 160 KB of LDS as dynamic shared memory
+// (done once per kernel instantiation).
 template <auto Kernel>
 void allow_lds() {
   static const hipError_t once = hipFuncSetAttribute(reinterpret_cast<const void*>(Kernel),
@@ -500,7 +671,8 @@ struct BlocksFwd {
                         int scale, hipStream_t s) {
     using B = BlockNtt<LOGM, LOGE>;
     allow_lds<k_blocks<LOGM, LOGE, false>>();
-    k_blocks<LOGM, LOGE, false><<<dim3(1u << (tb.log_n - LOGM), nl, items), dim3(B::T), block_lds<LOGM, LOGE>(), s>>>(tb, src, dst, first, nl, scale);
+    k_blocks<LOGM, LOGE, false><<<dim3(1u << (tb.log_n - LOGM), nl, items), dim3(B::T), block_lds<LOGM, LOGE>(), s>>>(
+        tb, src, dst, first, nl, scale);
     return hipGetLastError();
   }
 };
@@ -510,7 +682,8 @@ struct BlocksInv {
                         int scale, hipStream_t s) {
     using B = BlockNtt<LOGM, LOGE>;
     allow_lds<k_blocks<LOGM, LOGE, true>>();
-    k_blocks<LOGM, LOGE, true><<<dim3(1u << (tb.log_n - LOGM), nl, items), dim3(B::T), block_lds<LOGM, LOGE>(), s>>>(tb, src, dst, first, nl, scale);
+    k_blocks<LOGM, LOGE, true><<<dim3(1u << (tb.log_n - LOGM), nl, items), dim3(B::T), block_lds<LOGM, LOGE>(), s>>>(
+        tb, src, dst, first, nl, scale);
     return hipGetLastError();
   }
 };
@@ -518,9 +691,10 @@ template <int LOGR>
 struct ModupCols {
   static hipError_t run(const DevTables& tb, const uint64_t* t1, uint64_t* ext1, int j0, int nj, int nslots,
                         int slot_stride, int tgt0, int tgt1, int items, int log_m, hipStream_t s) {
-    const size_t lds = sizeof(uint64_t) * (size_t)tb.alpha * (1 << LOGR) * TC;
     allow_lds<k_modup_cols<LOGR>>();
-    k_modup_cols<LOGR><<<col_grid(log_m, nj, items), dim3(TC), lds, s>>>(tb, t1, ext1, j0, nslots, slot_stride, tgt0, tgt1, log_m);
+    const size_t lds = sizeof(double) * (size_t)tb.alpha * (1 << LOGR) * TC;
+    k_modup_cols<LOGR><<<col_grid(log_m, nj, items), dim3(CT), lds, s>>>(tb, t1, ext1, j0, nslots, slot_stride, tgt0,
+                                                                         tgt1, log_m);
     return hipGetLastError();
   }
 };
@@ -531,7 +705,9 @@ struct KeymultBlocks {
                         int accumulate, int finalize, hipStream_t s) {
     using B = BlockNtt<LOGM, LOGE>;
     allow_lds<k_keymult_blocks<LOGM, LOGE>>();
-    k_keymult_blocks<LOGM, LOGE><<<dim3(1u << (tb.log_n - LOGM), tgt1 - tgt0, items), dim3(B::T), block_lds<LOGM, LOGE>(), s>>>(tb, d, ext1, evk, acc, j0, j1, nslots, slot_stride, tgt0, accumulate, finalize);
+    k_keymult_blocks<LOGM, LOGE><<<dim3(1u << (tb.log_n - LOGM), tgt1 - tgt0, items), dim3(B::T),
+                                   block_lds<LOGM, LOGE>(), s>>>(tb, d, ext1, evk, acc, j0, j1, nslots, slot_stride,
+                                                                 tgt0, accumulate, finalize);
     return hipGetLastError();
   }
 };
@@ -539,9 +715,9 @@ template <int LOGR>
 struct ModdownCols {
   static hipError_t run(const DevTables& tb, const uint64_t* accp, uint64_t* t2, int tgt0, int tgt1, int items,
                         int log_m, hipStream_t s) {
-    const size_t lds = sizeof(uint64_t) * (size_t)tb.k * (1 << LOGR) * TC;
     allow_lds<k_moddown_cols<LOGR>>();
-    k_moddown_cols<LOGR><<<col_grid(log_m, 2, items), dim3(TC), lds, s>>>(tb, accp, t2, tgt0, tgt1, log_m);
+    const size_t lds = sizeof(uint64_t) * (size_t)tb.k * (1 << LOGR) * TC;
+    k_moddown_cols<LOGR><<<col_grid(log_m, 2, items), dim3(CT), lds, s>>>(tb, accp, t2, tgt0, tgt1, log_m);
     return hipGetLastError();
   }
 };
@@ -551,7 +727,8 @@ struct ModdownBlocks {
                         int tgt1, int items, hipStream_t s) {
     using B = BlockNtt<LOGM, LOGE>;
     allow_lds<k_moddown_blocks<LOGM, LOGE>>();
-    k_moddown_blocks<LOGM, LOGE><<<dim3(1u << (tb.log_n - LOGM), tgt1 - tgt0, items * 2), dim3(B::T), block_lds<LOGM, LOGE>(), s>>>(tb, t2, acc, out, tgt0);
+    k_moddown_blocks<LOGM, LOGE><<<dim3(1u << (tb.log_n - LOGM), tgt1 - tgt0, items * 2), dim3(B::T),
+                                   block_lds<LOGM, LOGE>(), s>>>(tb, t2, acc, out, tgt0);
     return hipGetLastError();
   }
 };
@@ -560,7 +737,8 @@ struct ExtBlocks {
   static hipError_t run(const DevTables& tb, uint64_t* ext, int items, hipStream_t s) {
     using B = BlockNtt<LOGM, LOGE>;
     allow_lds<k_ext_blocks<LOGM, LOGE>>();
-    k_ext_blocks<LOGM, LOGE><<<dim3(1u << (tb.log_n - LOGM), tb.nl, items * tb.ndig), dim3(B::T), block_lds<LOGM, LOGE>(), s>>>(tb, ext);
+    k_ext_blocks<LOGM, LOGE><<<dim3(1u << (tb.log_n - LOGM), tb.nl, items * tb.ndig), dim3(B::T),
+                               block_lds<LOGM, LOGE>(), s>>>(tb, ext);
     return hipGetLastError();
   }
 };
@@ -569,7 +747,8 @@ struct PBlocksInv {
   static hipError_t run(const DevTables& tb, const uint64_t* acc, uint64_t* accp, int items, hipStream_t s) {
     using B = BlockNtt<LOGM, LOGE>;
     allow_lds<k_pblocks_inv<LOGM, LOGE>>();
-    k_pblocks_inv<LOGM, LOGE><<<dim3(1u << (tb.log_n - LOGM), tb.k, items * 2), dim3(B::T), block_lds<LOGM, LOGE>(), s>>>(tb, acc, accp);
+    k_pblocks_inv<LOGM, LOGE><<<dim3(1u << (tb.log_n - LOGM), tb.k, items * 2), dim3(B::T),
+                                block_lds<LOGM, LOGE>(), s>>>(tb, acc, accp);
     return hipGetLastError();
   }
 };
@@ -577,6 +756,10 @@ struct PBlocksInv {
 }  // namespace
 
 // ------------------------------------------------------------ launchers
+
+// The column kernels stage count * 2^log_r values per column in LDS (64
+// columns per workgroup, 8 bytes each, at most 160 KB).
+int stage_cap(int count, int log_r) { return (size_t)count * ((size_t)1 << log_r) * 64 * 8 <= 160 * 1024 ? 1 : 0; }
 
 hipError_t launch_ntt(const DevTables& tb, int log_r, uint64_t* x, int first, int nlimbs, int items, hipStream_t s) {
   const int log_m = tb.log_n - log_r;
@@ -606,8 +789,8 @@ hipError_t launch_modup_cols(const DevTables& tb, int log_r, const uint64_t* t1,
 hipError_t launch_keymult_blocks(const DevTables& tb, int log_r, const uint64_t* d, const uint64_t* ext1,
                                  const uint64_t* evk, uint64_t* acc, int j0, int j1, int nslots, int slot_stride,
                                  int tgt0, int tgt1, int items, int accumulate, int finalize, hipStream_t s) {
-  return by_logm<KeymultBlocks>(tb.log_n - log_r, tb, d, ext1, evk, acc, j0, j1, nslots, slot_stride, tgt0, tgt1,
-                                items, accumulate, finalize, s);
+  return by_logm_k3<KeymultBlocks>(tb.log_n - log_r, tb, d, ext1, evk, acc, j0, j1, nslots, slot_stride, tgt0, tgt1,
+                                   items, accumulate, finalize, s);
 }
 
 hipError_t launch_moddown_cols(const DevTables& tb, int log_r, const uint64_t* accp, uint64_t* t2, int tgt0,

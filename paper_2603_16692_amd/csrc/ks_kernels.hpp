@@ -9,6 +9,10 @@
 
 namespace ks {
 
+// Nonzero when the column kernels can stage `count` source limbs of 2^log_r
+// rows each in LDS.
+int stage_cap(int count, int log_r);
+
 // Two-pass transforms of x [items][nlimbs][N], limb r over prime first + r.
 hipError_t launch_ntt(const DevTables& tb, int log_r, uint64_t* x, int first, int nlimbs, int items, hipStream_t s);
 hipError_t launch_intt(const DevTables& tb, int log_r, uint64_t* x, int first, int nlimbs, int items, hipStream_t s);
