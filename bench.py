@@ -67,6 +67,11 @@ def main():
     ap.add_argument("--batch", type=int, default=0, help="override the workload's batch size")
     ap.add_argument("--plan", default="", help="dataflow[,chunks[,log_r]] e.g. DPOB or DSOC,2,3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="use the library's default plan instead of tuning")
+    ap.add_argument("--tune-plans", type=int, default=0, help="candidate plans the tuner times (0 = all)")
+    ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay measurement")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only time a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     args = ap.parse_args()
 
@@ -81,6 +86,22 @@ def main():
     import paper_2603_16692_amd as ks
     from synth import ciphertext_batch, uniform_key
 
+    if args.copy_calibration:
+        n = 1 << 27  # 2^27 int64 words = 1 GiB
+        src = torch.ones(n, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        ev = ks.HipEvents(2)
+        for _ in range(2):
+            dst.copy_(src)
+        ev.record(0)
+        dst.copy_(src)
+        ev.record(1)
+        torch.cuda.synchronize()
+        ms = ev.elapsed_ms(0, 1)
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "ms": round(ms, 4),
+                          "GBs": round(2 * n * 8 / (ms / 1e3) / 1e9, 1)}))
+        return
+
     dnum, log_n, ell, batch, desc = WORKLOADS[args.workload]
     if args.batch:
         batch = args.batch
@@ -93,17 +114,31 @@ def main():
         parts = args.plan.split(",")
         df = {"DSOB": ks.DSOB, "DPOB": ks.DPOB, "DSOC": ks.DSOC, "DPOC": ks.DPOC, "STAGED": ks.STAGED}[parts[0]]
         chunks = int(parts[1]) if len(parts) > 1 else 1
-        log_r = int(parts[2]) if len(parts) > 2 else 0
+        log_r = int(parts[2]) if len(parts) > 2 else -1
         plan = ks.make_plan(df, chunks, log_r)
-    else:
-        plan = G.default_plan(batch)
 
     to_dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda")
     d = to_dev(ciphertext_batch(G.moduli[:ell], G.n, batch))
     evk = to_dev(uniform_key(G.moduli, G.n, G.ndig))
     out = torch.empty((batch, 2, ell, G.n), dtype=torch.int64, device="cuda")
-    ws = G.workspace(batch, plan)
     stream = torch.cuda.current_stream()
+
+    tuning = None
+    if plan is None and args.no_tune:
+        plan = G.default_plan(batch)
+    elif plan is None:
+        # per-parameter dataflow choice by measurement (untimed setup)
+        from paper_2603_16692_amd import autotune
+        cands = autotune.prior_order(G, batch, autotune.candidate_plans(G, batch))
+        plan, results = autotune.tune(G, d, evk, batch, plans=cands[:args.tune_plans] if args.tune_plans else cands,
+                                      reps=3, trials=2)
+        ranked = sorted(results, key=lambda r: r["ms"])
+        tuning = {"plans_tried": len(results), "best": ranked[0]["name"],
+                  "best_ms": round(ranked[0]["ms"], 4), "worst": ranked[-1]["name"],
+                  "worst_ms": round(ranked[-1]["ms"], 4),
+                  "default_ms": round(next((r["ms"] for r in results
+                                            if tuple(r["plan"]) == G.default_plan(batch).key()), float("nan")), 4)}
+    ws = G.workspace(batch, plan)
 
     for _ in range(args.warmup):
         G.keyswitch(d, evk, out, batch, ws, plan)
@@ -158,6 +193,24 @@ def main():
         torch.cuda.synchronize()
         plain = reps / (pe.elapsed_ms(0, 1) / 1e3)
 
+    # the same step replayed from a captured HIP graph
+    graph_rate = None
+    if not args.no_graph:
+        gs = torch.cuda.Stream()
+        gs.wait_stream(stream)
+        with torch.cuda.stream(gs):
+            g = G.graph(d, evk, out, batch, ws, plan, stream=gs)
+            for _ in range(2):
+                g.launch(gs)
+            ge = ks.HipEvents(2)
+            ge.record(0, gs)
+            for _ in range(args.steps):
+                g.launch(gs)
+            ge.record(1, gs)
+        torch.cuda.synchronize()
+        graph_rate = batch * args.steps / (ge.elapsed_ms(0, 1) / 1e3)
+        del g
+
     # roofline of the dominant kernel: its algorithmic bytes per step over its
     # time per step (= per launch bytes over the average launch time)
     dom_avg_ms = sum(dom_ms) / len(dom_ms)
@@ -199,6 +252,8 @@ def main():
         "config": {"workload": desc, "dnum": dnum, "N": G.n, "L": ell, "k": G.k, "batch": batch,
                    "plan": repr(plan), "launches_per_step": len(kinds)},
         "plain_single_ks_per_s": round(plain, 2) if plain else None,
+        "graph_ks_per_s": round(graph_rate, 2) if graph_rate else None,
+        "autotune": tuning,
         "latency_ms": {"p50": round(percentile(step_ms, 50), 4), "p99": round(percentile(step_ms, 99), 4)},
         "ks_algorithmic_GBs": round(ks_bytes * value / 1e9, 1),
         "breakdown_ms": {ks.KIND_NAMES[k]: round(v, 4) for k, v in sorted(per_kind.items())},

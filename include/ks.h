@@ -71,7 +71,8 @@ typedef struct ks_params ks_params; /* opaque, immutable after creation */
 typedef struct {
   int dataflow; /* KS_DSOB .. KS_STAGED */
   int chunks;   /* output partitions for KS_DSOC / KS_DPOC (1..64), else ignored */
-  int log_r;    /* NTT split N = 2^log_r * M (rows per column pass), 0 = default */
+  int log_r;    /* NTT split N = 2^log_r * M: 2^log_r rows per column, blocks of M
+                   coefficients (0 = one block pass, up to 5); negative = default */
   int flags;    /* reserved, must be 0 */
 } ks_plan;
 

@@ -111,7 +111,8 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def make_plan(dataflow=DPOB, chunks=1, log_r=0):
+def make_plan(dataflow=DPOB, chunks=1, log_r=-1):
+    """A plan; log_r < 0 selects the library's default NTT split."""
     return Plan(dataflow, chunks, log_r, 0)
 
 

@@ -1,0 +1,176 @@
+"""Per-parameter choice of the KeySwitch dataflow (DSOB / DPOB / DSOC / DPOC).
+
+The paper's finding (Quantitative Analysis section, Fig. 4) is that the best
+dataflow depends on (dnum, N, L) and on the GPU: as the on-chip footprint of a
+dataflow (Qualitative Analysis section, Table III and Fig. 3) outgrows the
+cache, the best choice moves to the dataflow with the next smaller footprint
+(roughly when the cache holds less than about twice the footprint). This
+module turns that finding into a per-parameter choice by measurement: it
+enumerates the valid plans (dataflow x chunks x NTT split), orders them by the
+footprint prior, times each on the device, keeps only plans whose output is
+bit-identical to the reference plan's, and caches the fastest per
+(GPU architecture, ROCm version, dnum, N, L, batch).
+
+On MI355X the paper's "L2" maps to two levels: a private 4 MB L2 per XCD (32 MB
+in all, not shared across XCDs) and the 256 MB MALL (Infinity Cache) shared by
+every XCD, through which data written by one kernel and read by the next
+passes. The prior therefore compares footprints with the MALL.
+"""
+import json
+import os
+import statistics
+
+import torch
+
+from . import DPOB, DPOC, DSOB, DSOC, STAGED, DATAFLOW_NAMES, HipEvents, KsError, make_plan
+
+WORD = 8
+MALL_BYTES = 256 << 20
+L2_PER_XCD_BYTES = 4 << 20
+CHUNK_RANGE = range(2, 11)  # the paper searches chunks in 2..10 (Quantitative Analysis section)
+
+
+def footprint_bytes(dnum: int, n: int, ell: int, dataflow: int, chunks: int = 1, batch: int = 1) -> int:
+    """The paper's on-chip footprint model: N*L words for DigitSerial, times
+    dnum for DigitParallel, divided by `chunks` for OutputChunked (Table III),
+    times the batch. (2, 2^15, 10) under DPOB gives 2 * 2^15 * 10 * 8 B."""
+    f = n * ell * WORD * batch
+    if dataflow in (DPOB, DPOC):
+        f *= dnum
+    if dataflow in (DSOC, DPOC):
+        f //= max(1, chunks)
+    return f
+
+
+def candidate_plans(params, batch: int, chunk_range=CHUNK_RANGE):
+    """Every plan libks accepts for these parameters and batch."""
+    plans = []
+    for log_r in range(0, 6):
+        log_m = params.log_n - log_r
+        if log_m < 3 or log_m > 14:
+            continue
+        for df in (DSOB, DPOB, STAGED):
+            plans.append(make_plan(df, 1, log_r))
+        for df in (DSOC, DPOC):
+            for c in chunk_range:
+                if c <= params.ell:
+                    plans.append(make_plan(df, c, log_r))
+    valid = []
+    for p in plans:
+        try:
+            params.workspace_bytes(batch, p)
+            valid.append(p)
+        except KsError:
+            pass
+    return valid
+
+
+def prior_order(params, batch: int, plans, cache_bytes: int = MALL_BYTES):
+    """Order plans by the footprint prior: the largest-parallelism plan whose
+    footprint stays within half of the cache comes first (the paper's 2x
+    rule), then the others by how far their footprint is from that target."""
+    def key(p):
+        f = footprint_bytes(params.dnum, params.n, params.ell, p.dataflow if p.dataflow != STAGED else DPOB,
+                            p.chunks, batch)
+        fits = f * 2 <= cache_bytes
+        launches = params.launch_count(batch, p)
+        return (0 if fits else 1, launches if fits else f, p.log_r)
+    return sorted(plans, key=key)
+
+
+def _cache_key(params, batch: int) -> str:
+    arch = torch.cuda.get_device_properties(0).gcnArchName if torch.cuda.is_available() else "cpu"
+    rocm = getattr(torch.version, "hip", None) or "none"
+    return f"{arch}|rocm{rocm}|dnum{params.dnum}|logn{params.log_n}|L{params.ell}|B{batch}"
+
+
+def default_cache_path() -> str:
+    return os.environ.get("KS_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "ks_autotune.json"))
+
+
+def load_cache(path: str = None) -> dict:
+    path = path or default_cache_path()
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(cache: dict, path: str = None) -> None:
+    path = path or default_cache_path()
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def time_plan(params, d, evk, out, batch: int, plan, reps: int = 5, trials: int = 3, stream=None) -> float:
+    """Median over trials of the mean time (ms) of `reps` back-to-back KeySwitch calls."""
+    ws = params.workspace(batch, plan)
+    params.keyswitch(d, evk, out, batch, ws, plan, stream=stream)
+    ev = HipEvents(2)
+    times = []
+    for _ in range(trials):
+        ev.record(0, stream)
+        for _ in range(reps):
+            params.keyswitch(d, evk, out, batch, ws, plan, stream=stream)
+        ev.record(1, stream)
+        torch.cuda.synchronize()
+        times.append(ev.elapsed_ms(0, 1) / reps)
+    return statistics.median(times)
+
+
+def tune(params, d, evk, batch: int, plans=None, reps: int = 5, trials: int = 3, max_plans: int = None,
+         cache: dict = None, verbose: bool = False):
+    """Time the candidate plans on (d, evk) and return (best_plan, results).
+
+    results is a list of {"plan", "ms", "ks_per_s", "bit_exact"} in the order
+    tried. A plan counts only if its output equals the reference plan's (the
+    default plan, itself checked against the oracle by the test suite)
+    element for element. With `cache`, the winner is stored under this
+    device, ROCm version, parameter set and batch."""
+    if plans is None:
+        plans = prior_order(params, batch, candidate_plans(params, batch))
+    if max_plans:
+        plans = plans[:max_plans]
+    out = torch.empty((batch, 2, params.ell, params.n), dtype=torch.int64, device=d.device)
+    ref_plan = params.default_plan(batch)
+    params.keyswitch(d, evk, out, batch, params.workspace(batch, ref_plan), ref_plan)
+    torch.cuda.synchronize()
+    ref = out.clone()
+    results, best, best_ms = [], None, float("inf")
+    for p in plans:
+        out.fill_(0)
+        ms = time_plan(params, d, evk, out, batch, p, reps, trials)
+        exact = bool(torch.equal(out, ref))
+        results.append({"plan": [p.dataflow, p.chunks, p.log_r], "name": repr(p), "ms": ms,
+                        "ks_per_s": batch / ms * 1e3, "bit_exact": exact})
+        if verbose:
+            print(f"  {p!r}: {ms:.4f} ms, {batch / ms * 1e3:.1f} KS/s, bit-exact={exact}", flush=True)
+        if exact and ms < best_ms:
+            best, best_ms = p, ms
+    if best is None:
+        raise RuntimeError("no candidate plan reproduced the reference output")
+    if cache is not None:
+        cache[_cache_key(params, batch)] = {"plan": [best.dataflow, best.chunks, best.log_r], "ms": best_ms,
+                                             "name": repr(best)}
+    return best, results
+
+
+def cached_plan(params, batch: int, cache: dict):
+    """The cached winner for this device and parameter set, or None."""
+    e = cache.get(_cache_key(params, batch))
+    if not e:
+        return None
+    p = make_plan(*e["plan"])
+    try:
+        params.workspace_bytes(batch, p)
+    except KsError:
+        return None
+    return p
+
+
+def describe(plan) -> str:
+    return f"{DATAFLOW_NAMES.get(plan.dataflow, plan.dataflow)}(chunks={plan.chunks}, log_r={plan.log_r})"

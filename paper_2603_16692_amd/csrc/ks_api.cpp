@@ -67,7 +67,12 @@ int check_ptr(const void* p) {
   return KS_OK;
 }
 
-int default_log_r(int log_n) { return log_n > 13 ? log_n - 13 : 0; }
+// Default NTT split: blocks of 2^12 coefficients from N = 2^14 up, 2^10 below
+// (enough workgroups for a single ciphertext), one pass for tiny N.
+int default_log_r(int log_n) {
+  if (log_n >= 14) return log_n - 12;
+  return log_n >= 10 ? log_n - 10 : 0;
+}
 
 // Plan validity for these parameters: the NTT split must be compiled and the
 // BConv sources of the column kernels must fit their register staging.
@@ -75,12 +80,11 @@ int resolve_plan(const ks_params* p, const ks_plan* in, ks_plan& out) {
   if (in) {
     out = *in;
   } else {
-    out = ks_plan{KS_DPOB, 1, 0, 0};
+    out = ks_plan{KS_DPOB, 1, -1, 0};
   }
   if (out.flags != 0) return KS_EUNSUP;
   if (out.dataflow < KS_DSOB || out.dataflow > KS_STAGED) return KS_EUNSUP;
-  if (out.log_r == 0) out.log_r = default_log_r(p->hp.log_n);
-  if (out.log_r < 0) out.log_r = 0;
+  if (out.log_r < 0) out.log_r = default_log_r(p->hp.log_n);
   const int log_m = p->hp.log_n - out.log_r;
   if (out.log_r > 5 || log_m < 3 || log_m > 14) return KS_EUNSUP;
   if (ks::stage_cap(p->hp.alpha, out.log_r) == 0 || ks::stage_cap(p->hp.k, out.log_r) == 0) return KS_EUNSUP;
@@ -350,7 +354,7 @@ int ks_modup(const ks_params* p, const uint64_t* d, uint64_t* ext, int batch, vo
   int rc;
   if ((rc = check_ptr(d)) != KS_OK || (rc = check_ptr(ext)) != KS_OK || (rc = check_ptr(ws)) != KS_OK) return rc;
   ks_plan pl;
-  const ks_plan staged{KS_STAGED, 1, 0, 0};
+  const ks_plan staged{KS_STAGED, 1, -1, 0};
   if ((rc = resolve_plan(p, &staged, pl)) != KS_OK) return rc;
   return run_modup(p, pl, d, ext, batch, reinterpret_cast<uint64_t*>(ws), (hipStream_t)stream);
 }
@@ -373,7 +377,7 @@ int ks_moddown(const ks_params* p, const uint64_t* acc, uint64_t* out, int batch
   int rc;
   if ((rc = check_ptr(acc)) != KS_OK || (rc = check_ptr(out)) != KS_OK || (rc = check_ptr(ws)) != KS_OK) return rc;
   ks_plan pl;
-  const ks_plan staged{KS_STAGED, 1, 0, 0};
+  const ks_plan staged{KS_STAGED, 1, -1, 0};
   if ((rc = resolve_plan(p, &staged, pl)) != KS_OK) return rc;
   const size_t accp_bytes = up256((size_t)batch * 2 * p->hp.nl * p->hp.n * sizeof(uint64_t));
   uint64_t* accp = reinterpret_cast<uint64_t*>(ws);

@@ -34,7 +34,7 @@ struct LimbC {
   double qd;           // q as a double (exact for the Q primes)
   double qinv;         // fl(1 / q)
   double ninv_d;       // balanced N^-1 mod q (Q primes)
-  double pad0, pad1;
+  uint64_t r64, r64_s; // 2^64 mod q with its Shoup companion
 };
 
 // Every table of one parameter set. Pointers are device addresses after
@@ -118,6 +118,15 @@ __device__ __forceinline__ double f_canon_d(double x, double q, double qinv) {
 }
 
 // ------------------------------------------------------ arithmetics
+
+// Read-only table loads through the constant address space: when the
+// address is the same for the whole wavefront (column-pass twiddles, BConv
+// constants) they become scalar loads into SGPRs, sparing vector registers;
+// otherwise they are ordinary vector loads.
+template <class T>
+__device__ __forceinline__ T ldc(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)(p);
+}
 
 struct Tw {
   uint64_t w, ws;

@@ -166,6 +166,8 @@ void build_tables(const HostParams& hp, std::vector<uint64_t>& blob, DevTables& 
     L.ninv = inv_prime(n % q, q);
     L.ninv_s = shoup(L.ninv, q);
     L.red_s = shoup(1, q);
+    L.r64 = (uint64_t)(((u128)1 << 64) % q);
+    L.r64_s = shoup(L.r64, q);
     L.qd = (double)q;
     L.qinv = 1.0 / (double)q;
     {

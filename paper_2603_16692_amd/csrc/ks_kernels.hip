@@ -151,11 +151,11 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_blocks(DevTables tb, c
 
 // ------------------------------------------------------------ ModUp (K2)
 
-// A column-pass workgroup: 4 waves over the same 64 columns (the 64 lanes).
-// Sources are converted once into LDS (wave w takes sources w, w+4, ...);
+// A column-pass workgroup: 8 waves over the same 64 columns (the 64 lanes).
+// Sources are converted once into LDS (wave w takes sources w, w+8, ...);
 // after a barrier the waves split the target limbs the same way, so the
 // registers a thread needs do not grow with the number of sources.
-constexpr int CW = 4;               // waves per column workgroup
+constexpr int CW = 8;               // waves per column workgroup
 constexpr int CT = CW * TC;         // threads per column workgroup
 
 // Digit j = j0 + blockIdx.y of item blockIdx.z, columns blockIdx.x*64 + lane:
@@ -166,7 +166,7 @@ constexpr int CT = CW * TC;         // threads per column workgroup
 // ext1 [items][nslots][nl][N] at slot (slot_stride ? j : 0). Q targets are
 // stored canonical, P targets in [0, 4q).
 template <int LOGR>
-__global__ __launch_bounds__(CT) void k_modup_cols(DevTables tb, const uint64_t* t1, uint64_t* ext1, int j0,
+__global__ __launch_bounds__(CT, LOGR <= 4 ? 4 : 2) void k_modup_cols(DevTables tb, const uint64_t* t1, uint64_t* ext1, int j0,
                                                    int nslots, int slot_stride, int tgt0, int tgt1, int log_m) {
   constexpr int R = 1 << LOGR;
   extern __shared__ double ys[];
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(CT) void k_modup_cols(DevTables tb, const uint64_t*
 #pragma unroll
       for (int r = 0; r < R; ++r) z[r] = 0.0;
       for (int s = 0; s < na; ++s) {
-        const double cst = tb.up_mat_d[(size_t)(lo + s) * ell + t];
+        const double cst = ldc(tb.up_mat_d + (size_t)(lo + s) * ell + t);
 #pragma unroll
         for (int r = 0; r < R; ++r) z[r] += f_mul(ys[(s * R + r) * TC + lane], cst, L.qd, L.qinv);
         if ((s & 7) == 7) {
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(CT) void k_modup_cols(DevTables tb, const uint64_t*
       for (int r = 0; r < R; ++r) z[r] = 0;
       for (int s = 0; s < na; ++s) {
         const size_t ci = 2 * ((size_t)(lo + s) * nl + t);
-        const uint64_t w = tb.up_mat[ci], ws = tb.up_mat[ci + 1];
+        const uint64_t w = ldc(tb.up_mat + ci), ws = ldc(tb.up_mat + ci + 1);
 #pragma unroll
         for (int r = 0; r < R; ++r) z[r] += reduce2(mul_shoup(d2u(ys[(s * R + r) * TC + lane]), w, ws, L.q), L.q);
         if ((s & 7) == 7) {  // keep the sum below 8q < 2^63
@@ -253,8 +253,12 @@ __global__ __launch_bounds__(CT) void k_modup_cols(DevTables tb, const uint64_t*
 // s_c += ext_j * evk[j][c]. Then v_c = s_c (+ the previous acc if
 // `accumulate`), stored canonical. With `finalize` and t a P limb, the inverse
 // block pass of ModDown runs on v_c and leaves [0, 2q) in acc.
-template <int LOGM, int LOGE>
-__global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_keymult_blocks(
+// QPATH selects the Q-limb (FP64) or the P-limb (integer) body; the two are
+// separate kernels so that each gets its own register allocation.
+// With 8 elements per thread at M >= 2^12 the kernel fits 128 registers,
+// which lets four waves share each SIMD.
+template <int LOGM, int LOGE, bool QPATH>
+__global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4 : 1) void k_keymult_blocks(
     DevTables tb, const uint64_t* d, const uint64_t* ext1, const uint64_t* evk, uint64_t* acc, int j0, int j1,
     int nslots, int slot_stride, int tgt0, int accumulate, int finalize) {
   using B = BlockNtt<LOGM, LOGE>;
@@ -269,7 +273,7 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_keymult_blocks(
   const size_t boff = (size_t)b * B::M;
   uint64_t* a0 = acc + (((size_t)item * 2 + 0) * nl + t) * N + boff;
   uint64_t* a1 = acc + (((size_t)item * 2 + 1) * nl + t) * N + boff;
-  if (t < tb.ell) {
+  if constexpr (QPATH) {
     const ArF A = arf(tb, L, t, false);
     double* ld = reinterpret_cast<double*>(lds);
     double s0[B::E], s1[B::E], v[B::E];
@@ -316,8 +320,7 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_keymult_blocks(
       a0[x] = f_canon(u0, L.qd, L.qinv);
       a1[x] = f_canon(u1, L.qd, L.qinv);
     }
-    return;
-  }
+  } else {
   const ArI A = ari(tb, L, t, false);
   uint64_t s0[B::E], s1[B::E], v[B::E];
 #pragma unroll
@@ -370,6 +373,7 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_keymult_blocks(
       a1[x] = s1[i];
     }
   }
+  }
 }
 
 // ---------------------------------------------------------- ModDown (K4)
@@ -382,7 +386,7 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_keymult_blocks(
 // y_hi [2^30 P/p_m] + y_lo [P/p_m] with y_m = y_hi 2^30 + y_lo; forward column
 // pass; t2 [items][2][ell][N] canonical.
 template <int LOGR>
-__global__ __launch_bounds__(CT) void k_moddown_cols(DevTables tb, const uint64_t* accp, uint64_t* t2, int tgt0,
+__global__ __launch_bounds__(CT, LOGR <= 4 ? 4 : 2) void k_moddown_cols(DevTables tb, const uint64_t* accp, uint64_t* t2, int tgt0,
                                                      int tgt1, int log_m) {
   constexpr int R = 1 << LOGR;
   extern __shared__ uint64_t yl[];
@@ -704,10 +708,22 @@ struct KeymultBlocks {
                         uint64_t* acc, int j0, int j1, int nslots, int slot_stride, int tgt0, int tgt1, int items,
                         int accumulate, int finalize, hipStream_t s) {
     using B = BlockNtt<LOGM, LOGE>;
-    allow_lds<k_keymult_blocks<LOGM, LOGE>>();
-    k_keymult_blocks<LOGM, LOGE><<<dim3(1u << (tb.log_n - LOGM), tgt1 - tgt0, items), dim3(B::T),
-                                   block_lds<LOGM, LOGE>(), s>>>(tb, d, ext1, evk, acc, j0, j1, nslots, slot_stride,
-                                                                 tgt0, accumulate, finalize);
+    const int qend = tgt1 < tb.ell ? tgt1 : tb.ell;
+    if (tgt0 < qend) {
+      allow_lds<k_keymult_blocks<LOGM, LOGE, true>>();
+      k_keymult_blocks<LOGM, LOGE, true><<<dim3(1u << (tb.log_n - LOGM), qend - tgt0, items), dim3(B::T),
+                                           block_lds<LOGM, LOGE>(), s>>>(tb, d, ext1, evk, acc, j0, j1, nslots,
+                                                                         slot_stride, tgt0, accumulate, finalize);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    const int pbeg = tgt0 > tb.ell ? tgt0 : tb.ell;
+    if (pbeg < tgt1) {
+      allow_lds<k_keymult_blocks<LOGM, LOGE, false>>();
+      k_keymult_blocks<LOGM, LOGE, false><<<dim3(1u << (tb.log_n - LOGM), tgt1 - pbeg, items), dim3(B::T),
+                                            block_lds<LOGM, LOGE>(), s>>>(tb, d, ext1, evk, acc, j0, j1, nslots,
+                                                                          slot_stride, pbeg, accumulate, finalize);
+    }
     return hipGetLastError();
   }
 };

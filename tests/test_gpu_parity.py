@@ -111,7 +111,7 @@ def test_modup_keymult_moddown(ks, dnum, log_n, ell):
 
 def _plans(ks, P, log_n):
     plans = []
-    for log_r in range(0, 5):
+    for log_r in range(0, 6):
         log_m = log_n - log_r
         if log_m < 3 or log_m > 14:
             continue
