@@ -32,20 +32,31 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_bytes(G, plan, batch, kind):
-    """Algorithmic HBM bytes of one launch of `kind` under a one-chunk plan:
-    each input the kernel needs read once, each output written once."""
+    """Algorithmic HBM bytes of all launches of `kind` in one step: each input
+    a kernel needs read once, each output written once (the key once per
+    batch). Digit-parallel plans run KeyMult for the P limbs only and fold the
+    Q-limb KeyMult into ModDown's last block pass."""
+    import paper_2603_16692_amd as ks
     W, N, B = 8, G.n, batch
     ell, nl, k, nd, a = G.ell, G.nl, G.k, G.ndig, G.alpha
+    own = [len(range(j * a, min((j + 1) * a, ell))) for j in range(nd)]
+    ext_q = sum(ell - o for o in own)   # raised Q limbs over all digits
+    ext_p = nd * k                      # raised P limbs over all digits
+    dp = plan.dataflow in (ks.DPOB, ks.DPOC)
     if kind == 0:    # inverse block pass of d
         return 2 * B * ell * N * W
     if kind == 1:    # ModUp columns: read the digits, write the raised limbs
-        return B * ell * N * W + B * sum(nl - len(range(j * a, min((j + 1) * a, ell))) for j in range(nd)) * N * W
-    if kind == 2:    # block pass + KeyMult: raised limbs and d in, key in once, acc out
-        ext = B * sum(nl - len(range(j * a, min((j + 1) * a, ell))) for j in range(nd)) * N * W
-        return ext + B * ell * N * W + 2 * nd * nl * N * W + 2 * B * nl * N * W
+        return B * ell * N * W + B * (ext_q + ext_p) * N * W
+    if kind == 2:    # block pass + KeyMult
+        if dp:       # P limbs: raised limbs in, key in once, acc_P out
+            return B * ext_p * N * W + 2 * nd * k * N * W + 2 * B * k * N * W
+        return B * (ext_q + ext_p) * N * W + B * ell * N * W + 2 * nd * nl * N * W + 2 * B * nl * N * W
     if kind == 3:    # ModDown columns: P limbs in, Q limbs out
         return 2 * B * k * N * W + 2 * B * ell * N * W
-    if kind == 4:    # ModDown blocks: t2 and acc_Q in, out written
+    if kind == 4:    # ModDown blocks: t2 in, out written; acc_Q in, or (DP) the Q KeyMult inputs
+        if dp:
+            return 2 * B * ell * N * W + B * ext_q * N * W + B * ell * N * W + 2 * nd * ell * N * W \
+                + 2 * B * ell * N * W
         return 3 * 2 * B * ell * N * W
     return None
 

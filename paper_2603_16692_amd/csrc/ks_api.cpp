@@ -159,6 +159,17 @@ int run_moddown(const ks_params* p, const ks_plan& plan, const uint64_t* acc, ui
   return KS_OK;
 }
 
+// Number of kernels launch_keymult_blocks starts for targets [a, b).
+int km_kernels(const ks::DevTables& tb, int a, int b, bool q_part) {
+  const int qend = std::min(b, tb.ell), pbeg = std::max(a, tb.ell);
+  return ((q_part && a < qend) ? 1 : 0) + (pbeg < b ? 1 : 0);
+}
+
+// The fused plans. Digit-serial plans (DSOB, DSOC) accumulate acc over
+// digits and finish with ModDown's block pass; digit-parallel plans (DPOB,
+// DPOC) run KeyMult only for the P limbs up front (their sum feeds ModDown's
+// BConv) and fold the Q-limb KeyMult into ModDown's last block pass, so acc_Q
+// never goes through memory.
 int run_fused(const ks_params* p, const ks_plan& plan, const uint64_t* d, const uint64_t* evk, uint64_t* out,
               int batch, char* ws, hipStream_t s, int* launches) {
   const ks::DevTables& tb = p->tb;
@@ -179,19 +190,28 @@ int run_fused(const ks_params* p, const ks_plan& plan, const uint64_t* d, const 
     if (a == b) continue;
     if (dp) {
       if (run) {
-        KS_TRY(traced(KS_K_MODUP_COLS, s, [&] { return ks::launch_modup_cols(tb, plan.log_r, t1, ext1, 0, tb.ndig, L.nslots, 1, a, b, batch, s); }));
-        KS_TRY(traced(KS_K_KEYMULT_BLOCKS, s, [&] { return ks::launch_keymult_blocks(tb, plan.log_r, d, ext1, evk, acc, 0, tb.ndig, L.nslots, 1, a, b, batch, 0,
-                                         1, s); }));
+        KS_TRY(traced(KS_K_MODUP_COLS, s, [&] {
+          return ks::launch_modup_cols(tb, plan.log_r, t1, ext1, 0, tb.ndig, L.nslots, 1, a, b, batch, s);
+        }));
+        if (km_kernels(tb, a, b, false))
+          KS_TRY(traced(KS_K_KEYMULT_BLOCKS, s, [&] {
+            return ks::launch_keymult_blocks(tb, plan.log_r, d, ext1, evk, acc, 0, tb.ndig, L.nslots, 1, a, b, batch,
+                                             0, 1, 0, s);
+          }));
       }
-      count += 2;
+      count += 1 + km_kernels(tb, a, b, false);
     } else {
       for (int j = 0; j < tb.ndig; ++j) {
         if (run) {
-          KS_TRY(traced(KS_K_MODUP_COLS, s, [&] { return ks::launch_modup_cols(tb, plan.log_r, t1, ext1, j, 1, 1, 0, a, b, batch, s); }));
-          KS_TRY(traced(KS_K_KEYMULT_BLOCKS, s, [&] { return ks::launch_keymult_blocks(tb, plan.log_r, d, ext1, evk, acc, j, j + 1, 1, 0, a, b, batch, j > 0,
-                                           j == tb.ndig - 1, s); }));
+          KS_TRY(traced(KS_K_MODUP_COLS, s, [&] {
+            return ks::launch_modup_cols(tb, plan.log_r, t1, ext1, j, 1, 1, 0, a, b, batch, s);
+          }));
+          KS_TRY(traced(KS_K_KEYMULT_BLOCKS, s, [&] {
+            return ks::launch_keymult_blocks(tb, plan.log_r, d, ext1, evk, acc, j, j + 1, 1, 0, a, b, batch, j > 0,
+                                             j == tb.ndig - 1, 1, s);
+          }));
         }
-        count += 2;
+        count += 1 + km_kernels(tb, a, b, true);
       }
     }
   }
@@ -201,7 +221,15 @@ int run_fused(const ks_params* p, const ks_plan& plan, const uint64_t* d, const 
     if (a == b) continue;
     if (run) {
       KS_TRY(traced(KS_K_MODDOWN_COLS, s, [&] { return ks::launch_moddown_cols(tb, plan.log_r, acc, t2, a, b, batch, s); }));
-      KS_TRY(traced(KS_K_MODDOWN_BLOCKS, s, [&] { return ks::launch_moddown_blocks(tb, plan.log_r, t2, acc, out, a, b, batch, s); }));
+      if (dp)
+        KS_TRY(traced(KS_K_MODDOWN_BLOCKS, s, [&] {
+          return ks::launch_moddown_km_blocks(tb, plan.log_r, d, ext1, evk, t2, out, 0, tb.ndig, L.nslots, 1, a, b,
+                                              batch, s);
+        }));
+      else
+        KS_TRY(traced(KS_K_MODDOWN_BLOCKS, s, [&] {
+          return ks::launch_moddown_blocks(tb, plan.log_r, t2, acc, out, a, b, batch, s);
+        }));
     }
     count += 2;
   }

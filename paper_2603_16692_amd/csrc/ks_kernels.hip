@@ -42,6 +42,26 @@ __device__ __forceinline__ uint64_t d2u(double v) {
   return (uint64_t)__double_as_longlong(v + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
 }
 
+// XCD-aware placement of block-pass workgroups. MI355X dispatches workgroup
+// w to XCD w mod 8, and each XCD has its own 4 MB L2. A block-pass "tile" is
+// one (limb, block) pair; the batch items of a tile read the same twiddles
+// and, in KeyMult, the same key blocks. The mapping below puts all items of a
+// tile on one XCD at consecutive dispatch slots, so those shared reads are
+// served by that XCD's L2 instead of going to HBM once per item.
+// Grid: 8 * ceil(ntiles / 8) * items workgroups (1-D).
+struct Tile {
+  int tile, item;
+  bool valid;
+};
+__device__ __forceinline__ Tile xcd_tile(int ntiles, int items) {
+  const int w = blockIdx.x;
+  const int xcd = w & 7, local = w >> 3;
+  const int item = local % items, unit = local / items;
+  const int tile = unit * 8 + xcd;
+  return Tile{tile, item, tile < ntiles};
+}
+inline unsigned xcd_grid(int ntiles, int items) { return (unsigned)(((ntiles + 7) / 8) * 8 * items); }
+
 // ------------------------------------------------------- standalone passes
 
 // Column pass of ks_ntt / ks_intt on x [items][nlimbs][N] (limb r uses prime
@@ -88,21 +108,25 @@ __global__ __launch_bounds__(TC) void k_cols(DevTables tb, uint64_t* x, int firs
   }
 }
 
-// Block pass of ks_ntt / ks_intt (and of d at the start of ModUp): block b of
-// limb first + blockIdx.y of item blockIdx.z, src -> dst (may alias).
+// Block pass of ks_ntt / ks_intt (and of d at the start of ModUp): one block
+// of one limb (first + l) of one item per workgroup (placed by xcd_tile),
+// src -> dst (may alias).
 // Forward: Q canonical in; P [0, 4q) in; canonical out. Inverse: canonical in;
 // out Q canonical, P [0, 2q); times N^-1 (canonical) when `scale` is set.
 template <int LOGM, int LOGE, bool INV>
 __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_blocks(DevTables tb, const uint64_t* src, uint64_t* dst,
-                                                                 int first, int nlimbs, int scale) {
+                                                                 int first, int nlimbs, int items, int scale) {
   using B = BlockNtt<LOGM, LOGE>;
   extern __shared__ uint64_t lds[];
-  const int tid = threadIdx.x, b = blockIdx.x;
-  const int limb = first + blockIdx.y;
-  const LimbC L = tb.limb[limb];
   const size_t N = (size_t)1 << tb.log_n;
-  const uint32_t B0 = (uint32_t)(N >> LOGM) + b;
-  const size_t off = ((size_t)blockIdx.z * nlimbs + blockIdx.y) * N + (size_t)b * B::M;
+  const int R = (int)(N >> LOGM);
+  const Tile tl = xcd_tile(R * nlimbs, items);
+  if (!tl.valid) return;
+  const int tid = threadIdx.x, b = tl.tile % R, lrel = tl.tile / R;
+  const int limb = first + lrel;
+  const LimbC L = tb.limb[limb];
+  const uint32_t B0 = (uint32_t)R + b;
+  const size_t off = ((size_t)tl.item * nlimbs + lrel) * N + (size_t)b * B::M;
   const uint64_t* s = src + off;
   uint64_t* d = dst + off;
   if (limb < tb.ell) {
@@ -248,7 +272,8 @@ __global__ __launch_bounds__(CT, LOGR <= 4 ? 4 : 2) void k_modup_cols(DevTables 
 
 // ---------------------------------------------------------- KeyMult (K3)
 
-// Block b of target limb t = tgt0 + blockIdx.y of item blockIdx.z: for every
+// One block b of one target limb t in [tgt0, tgt0 + ntgt) of one item per
+// workgroup (placed by xcd_tile): for every
 // digit j in [j0, j1): ext_j = (t in D_j) ? d : forward block pass of ext1;
 // s_c += ext_j * evk[j][c]. Then v_c = s_c (+ the previous acc if
 // `accumulate`), stored canonical. With `finalize` and t a P limb, the inverse
@@ -260,15 +285,18 @@ __global__ __launch_bounds__(CT, LOGR <= 4 ? 4 : 2) void k_modup_cols(DevTables 
 template <int LOGM, int LOGE, bool QPATH>
 __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4 : 1) void k_keymult_blocks(
     DevTables tb, const uint64_t* d, const uint64_t* ext1, const uint64_t* evk, uint64_t* acc, int j0, int j1,
-    int nslots, int slot_stride, int tgt0, int accumulate, int finalize) {
+    int nslots, int slot_stride, int tgt0, int ntgt, int items, int accumulate, int finalize) {
   using B = BlockNtt<LOGM, LOGE>;
   extern __shared__ uint64_t lds[];
-  const int tid = threadIdx.x, b = blockIdx.x;
-  const int t = tgt0 + blockIdx.y;
-  const int item = blockIdx.z;
-  const LimbC L = tb.limb[t];
   const size_t N = (size_t)1 << tb.log_n;
-  const uint32_t B0 = (uint32_t)(N >> LOGM) + b;
+  const int R = (int)(N >> LOGM);
+  const Tile tl = xcd_tile(R * ntgt, items);
+  if (!tl.valid) return;
+  const int tid = threadIdx.x, b = tl.tile % R;
+  const int t = tgt0 + tl.tile / R;
+  const int item = tl.item;
+  const LimbC L = tb.limb[t];
+  const uint32_t B0 = (uint32_t)R + b;
   const int nl = tb.nl;
   const size_t boff = (size_t)b * B::M;
   uint64_t* a0 = acc + (((size_t)item * 2 + 0) * nl + t) * N + boff;
@@ -444,20 +472,24 @@ __global__ __launch_bounds__(CT, LOGR <= 4 ? 4 : 2) void k_moddown_cols(DevTable
 
 // ---------------------------------------------------------- ModDown (K5)
 
-// Block b of Q limb i = tgt0 + blockIdx.y, item/component blockIdx.z = item*2+c:
+// One block b of one Q limb i in [tgt0, tgt0 + ntgt) of one (item, component)
+// pair ic = item*2 + c per workgroup (placed by xcd_tile):
 // forward block pass of t2 (canonical), then out = (acc_Q - v) * P^-1 (canonical).
 template <int LOGM, int LOGE>
 __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_moddown_blocks(DevTables tb, const uint64_t* t2,
                                                                          const uint64_t* acc, uint64_t* out,
-                                                                         int tgt0) {
+                                                                         int tgt0, int ntgt, int ics) {
   using B = BlockNtt<LOGM, LOGE>;
   extern __shared__ uint64_t lds[];
-  const int tid = threadIdx.x, b = blockIdx.x;
-  const int i = tgt0 + blockIdx.y;
-  const int ic = blockIdx.z;
-  const LimbC L = tb.limb[i];
   const size_t N = (size_t)1 << tb.log_n;
-  const uint32_t B0 = (uint32_t)(N >> LOGM) + b;
+  const int R = (int)(N >> LOGM);
+  const Tile tl = xcd_tile(R * ntgt, ics);
+  if (!tl.valid) return;
+  const int tid = threadIdx.x, b = tl.tile % R;
+  const int i = tgt0 + tl.tile / R;
+  const int ic = tl.item;
+  const LimbC L = tb.limb[i];
+  const uint32_t B0 = (uint32_t)R + b;
   const size_t boff = (size_t)b * B::M;
   const uint64_t* src = t2 + ((size_t)ic * tb.ell + i) * N + boff;
   double v[B::E];
@@ -472,6 +504,90 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_moddown_blocks(DevTabl
     const int x = B::cl_pos(tid, e);
     // |acc - v| <= 2.4q, |P^-1| <= q/2
     o[x] = f_canon(f_mul(u2d(a[x]) - v[e], pinv, L.qd, L.qinv), L.qd, L.qinv);
+  }
+}
+
+// One block b of one Q limb i in [tgt0, tgt0 + ntgt) of one item per workgroup
+// (placed by xcd_tile), both components:
+// the digit-parallel plans defer the Q-limb KeyMult to here, so acc_Q never
+// goes through HBM. s_c = -NTT(t2_c) + sum_j ext_j * evk[j][c] (ext_j = d on
+// the digit's own limbs, else the forward block pass of ext1), then
+// out_c = s_c * P^-1 (canonical).
+template <int LOGM, int LOGE>
+__global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4 : 1) void k_moddown_km_blocks(
+    DevTables tb, const uint64_t* d, const uint64_t* ext1, const uint64_t* evk, const uint64_t* t2, uint64_t* out,
+    int j0, int j1, int nslots, int slot_stride, int tgt0, int ntgt, int items) {
+  using B = BlockNtt<LOGM, LOGE>;
+  extern __shared__ uint64_t lds[];
+  double* ld = reinterpret_cast<double*>(lds);
+  const size_t N = (size_t)1 << tb.log_n;
+  const int R = (int)(N >> LOGM);
+  const Tile tl = xcd_tile(R * ntgt, items);
+  if (!tl.valid) return;
+  const int tid = threadIdx.x, b = tl.tile % R;
+  const int i = tgt0 + tl.tile / R;
+  const int item = tl.item;
+  const LimbC L = tb.limb[i];
+  const uint32_t B0 = (uint32_t)R + b;
+  const int nl = tb.nl, ell = tb.ell;
+  const size_t boff = (size_t)b * B::M;
+  const ArF A = arf(tb, L, i, false);
+  double s0[B::E], s1[B::E], v[B::E];
+  {
+    const uint64_t* src = t2 + (((size_t)item * 2 + 0) * ell + i) * N + boff;
+#pragma unroll
+    for (int e = 0; e < B::E; ++e) v[e] = u2d(src[B::fr_pos(tid, e)]);
+    B::fwd(A, v, ld, tid, B0);
+#pragma unroll
+    for (int e = 0; e < B::E; ++e) s0[e] = -v[e];
+  }
+  {
+    const uint64_t* src = t2 + (((size_t)item * 2 + 1) * ell + i) * N + boff;
+#pragma unroll
+    for (int e = 0; e < B::E; ++e) v[e] = u2d(src[B::fr_pos(tid, e)]);
+    B::fwd(A, v, ld, tid, B0);
+#pragma unroll
+    for (int e = 0; e < B::E; ++e) s1[e] = -v[e];
+  }
+  for (int j = j0; j < j1; ++j) {
+    const int lo = j * tb.alpha;
+    if (i >= lo && i < lo + tb.alpha) {
+      const uint64_t* src = d + ((size_t)item * ell + i) * N + boff;
+#pragma unroll
+      for (int e = 0; e < B::E; ++e) v[e] = u2d(src[B::cl_pos(tid, e)]);
+    } else {
+      const int slot = slot_stride ? j : 0;
+      const uint64_t* src = ext1 + (((size_t)item * nslots + slot) * nl + i) * N + boff;
+#pragma unroll
+      for (int e = 0; e < B::E; ++e) v[e] = u2d(src[B::fr_pos(tid, e)]);
+      B::fwd(A, v, ld, tid, B0);
+    }
+    const uint64_t* k0 = evk + (((size_t)j * 2 + 0) * nl + i) * N + boff;
+    const uint64_t* k1 = evk + (((size_t)j * 2 + 1) * nl + i) * N + boff;
+    // |v| <= 2q, key < q: each product is within 1.25q; the running sums start
+    // within 1.375q + 1 and are folded every 4 digits, so they stay below 2^53
+#pragma unroll
+    for (int e = 0; e < B::E; ++e) {
+      const int x = B::cl_pos(tid, e);
+      s0[e] += f_mul(v[e], u2d(k0[x]), L.qd, L.qinv);
+      s1[e] += f_mul(v[e], u2d(k1[x]), L.qd, L.qinv);
+    }
+    if (((j - j0) & 3) == 3) {
+#pragma unroll
+      for (int e = 0; e < B::E; ++e) {
+        s0[e] = f_red(s0[e], L.qd, L.qinv);
+        s1[e] = f_red(s1[e], L.qd, L.qinv);
+      }
+    }
+  }
+  const double pinv = tb.dn_pinv_d[i];
+  uint64_t* o0 = out + (((size_t)item * 2 + 0) * ell + i) * N + boff;
+  uint64_t* o1 = out + (((size_t)item * 2 + 1) * ell + i) * N + boff;
+#pragma unroll
+  for (int e = 0; e < B::E; ++e) {
+    const int x = B::cl_pos(tid, e);
+    o0[x] = f_canon(f_mul(f_red(s0[e], L.qd, L.qinv), pinv, L.qd, L.qinv), L.qd, L.qinv);
+    o1[x] = f_canon(f_mul(f_red(s1[e], L.qd, L.qinv), pinv, L.qd, L.qinv), L.qd, L.qinv);
   }
 }
 
@@ -675,8 +791,8 @@ struct BlocksFwd {
                         int scale, hipStream_t s) {
     using B = BlockNtt<LOGM, LOGE>;
     allow_lds<k_blocks<LOGM, LOGE, false>>();
-    k_blocks<LOGM, LOGE, false><<<dim3(1u << (tb.log_n - LOGM), nl, items), dim3(B::T), block_lds<LOGM, LOGE>(), s>>>(
-        tb, src, dst, first, nl, scale);
+    k_blocks<LOGM, LOGE, false><<<dim3(xcd_grid(nl << (tb.log_n - LOGM), items)), dim3(B::T),
+                                  block_lds<LOGM, LOGE>(), s>>>(tb, src, dst, first, nl, items, scale);
     return hipGetLastError();
   }
 };
@@ -686,8 +802,8 @@ struct BlocksInv {
                         int scale, hipStream_t s) {
     using B = BlockNtt<LOGM, LOGE>;
     allow_lds<k_blocks<LOGM, LOGE, true>>();
-    k_blocks<LOGM, LOGE, true><<<dim3(1u << (tb.log_n - LOGM), nl, items), dim3(B::T), block_lds<LOGM, LOGE>(), s>>>(
-        tb, src, dst, first, nl, scale);
+    k_blocks<LOGM, LOGE, true><<<dim3(xcd_grid(nl << (tb.log_n - LOGM), items)), dim3(B::T),
+                                 block_lds<LOGM, LOGE>(), s>>>(tb, src, dst, first, nl, items, scale);
     return hipGetLastError();
   }
 };
@@ -706,23 +822,25 @@ template <int LOGM, int LOGE>
 struct KeymultBlocks {
   static hipError_t run(const DevTables& tb, const uint64_t* d, const uint64_t* ext1, const uint64_t* evk,
                         uint64_t* acc, int j0, int j1, int nslots, int slot_stride, int tgt0, int tgt1, int items,
-                        int accumulate, int finalize, hipStream_t s) {
+                        int accumulate, int finalize, int q_part, hipStream_t s) {
     using B = BlockNtt<LOGM, LOGE>;
     const int qend = tgt1 < tb.ell ? tgt1 : tb.ell;
-    if (tgt0 < qend) {
+    if (q_part && tgt0 < qend) {
       allow_lds<k_keymult_blocks<LOGM, LOGE, true>>();
-      k_keymult_blocks<LOGM, LOGE, true><<<dim3(1u << (tb.log_n - LOGM), qend - tgt0, items), dim3(B::T),
+      k_keymult_blocks<LOGM, LOGE, true><<<dim3(xcd_grid((qend - tgt0) << (tb.log_n - LOGM), items)), dim3(B::T),
                                            block_lds<LOGM, LOGE>(), s>>>(tb, d, ext1, evk, acc, j0, j1, nslots,
-                                                                         slot_stride, tgt0, accumulate, finalize);
+                                                                         slot_stride, tgt0, qend - tgt0, items,
+                                                                         accumulate, finalize);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
     const int pbeg = tgt0 > tb.ell ? tgt0 : tb.ell;
     if (pbeg < tgt1) {
       allow_lds<k_keymult_blocks<LOGM, LOGE, false>>();
-      k_keymult_blocks<LOGM, LOGE, false><<<dim3(1u << (tb.log_n - LOGM), tgt1 - pbeg, items), dim3(B::T),
+      k_keymult_blocks<LOGM, LOGE, false><<<dim3(xcd_grid((tgt1 - pbeg) << (tb.log_n - LOGM), items)), dim3(B::T),
                                             block_lds<LOGM, LOGE>(), s>>>(tb, d, ext1, evk, acc, j0, j1, nslots,
-                                                                          slot_stride, pbeg, accumulate, finalize);
+                                                                          slot_stride, pbeg, tgt1 - pbeg, items,
+                                                                          accumulate, finalize);
     }
     return hipGetLastError();
   }
@@ -743,8 +861,21 @@ struct ModdownBlocks {
                         int tgt1, int items, hipStream_t s) {
     using B = BlockNtt<LOGM, LOGE>;
     allow_lds<k_moddown_blocks<LOGM, LOGE>>();
-    k_moddown_blocks<LOGM, LOGE><<<dim3(1u << (tb.log_n - LOGM), tgt1 - tgt0, items * 2), dim3(B::T),
-                                   block_lds<LOGM, LOGE>(), s>>>(tb, t2, acc, out, tgt0);
+    k_moddown_blocks<LOGM, LOGE><<<dim3(xcd_grid((tgt1 - tgt0) << (tb.log_n - LOGM), items * 2)), dim3(B::T),
+                                   block_lds<LOGM, LOGE>(), s>>>(tb, t2, acc, out, tgt0, tgt1 - tgt0, items * 2);
+    return hipGetLastError();
+  }
+};
+template <int LOGM, int LOGE>
+struct ModdownKmBlocks {
+  static hipError_t run(const DevTables& tb, const uint64_t* d, const uint64_t* ext1, const uint64_t* evk,
+                        const uint64_t* t2, uint64_t* out, int j0, int j1, int nslots, int slot_stride, int tgt0,
+                        int tgt1, int items, hipStream_t s) {
+    using B = BlockNtt<LOGM, LOGE>;
+    allow_lds<k_moddown_km_blocks<LOGM, LOGE>>();
+    k_moddown_km_blocks<LOGM, LOGE><<<dim3(xcd_grid((tgt1 - tgt0) << (tb.log_n - LOGM), items)), dim3(B::T),
+                                      block_lds<LOGM, LOGE>(), s>>>(tb, d, ext1, evk, t2, out, j0, j1, nslots,
+                                                                    slot_stride, tgt0, tgt1 - tgt0, items);
     return hipGetLastError();
   }
 };
@@ -804,9 +935,17 @@ hipError_t launch_modup_cols(const DevTables& tb, int log_r, const uint64_t* t1,
 
 hipError_t launch_keymult_blocks(const DevTables& tb, int log_r, const uint64_t* d, const uint64_t* ext1,
                                  const uint64_t* evk, uint64_t* acc, int j0, int j1, int nslots, int slot_stride,
-                                 int tgt0, int tgt1, int items, int accumulate, int finalize, hipStream_t s) {
+                                 int tgt0, int tgt1, int items, int accumulate, int finalize, int q_part,
+                                 hipStream_t s) {
   return by_logm_k3<KeymultBlocks>(tb.log_n - log_r, tb, d, ext1, evk, acc, j0, j1, nslots, slot_stride, tgt0, tgt1,
-                                   items, accumulate, finalize, s);
+                                   items, accumulate, finalize, q_part, s);
+}
+
+hipError_t launch_moddown_km_blocks(const DevTables& tb, int log_r, const uint64_t* d, const uint64_t* ext1,
+                                    const uint64_t* evk, const uint64_t* t2, uint64_t* out, int j0, int j1,
+                                    int nslots, int slot_stride, int tgt0, int tgt1, int items, hipStream_t s) {
+  return by_logm_k3<ModdownKmBlocks>(tb.log_n - log_r, tb, d, ext1, evk, t2, out, j0, j1, nslots, slot_stride, tgt0,
+                                     tgt1, items, s);
 }
 
 hipError_t launch_moddown_cols(const DevTables& tb, int log_r, const uint64_t* accp, uint64_t* t2, int tgt0,

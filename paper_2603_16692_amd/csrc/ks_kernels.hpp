@@ -21,9 +21,16 @@ hipError_t launch_intt_blocks(const DevTables& tb, int log_r, const uint64_t* sr
                               int items, hipStream_t s);
 hipError_t launch_modup_cols(const DevTables& tb, int log_r, const uint64_t* t1, uint64_t* ext1, int j0, int nj,
                              int nslots, int slot_stride, int tgt0, int tgt1, int items, hipStream_t s);
+// KeyMult over targets [tgt0, tgt1): one kernel for the Q limbs (skipped when
+// q_part is 0) and one for the P limbs.
 hipError_t launch_keymult_blocks(const DevTables& tb, int log_r, const uint64_t* d, const uint64_t* ext1,
                                  const uint64_t* evk, uint64_t* acc, int j0, int j1, int nslots, int slot_stride,
-                                 int tgt0, int tgt1, int items, int accumulate, int finalize, hipStream_t s);
+                                 int tgt0, int tgt1, int items, int accumulate, int finalize, int q_part,
+                                 hipStream_t s);
+// ModDown's last block pass with the Q-limb KeyMult of digits [j0, j1) folded in.
+hipError_t launch_moddown_km_blocks(const DevTables& tb, int log_r, const uint64_t* d, const uint64_t* ext1,
+                                    const uint64_t* evk, const uint64_t* t2, uint64_t* out, int j0, int j1,
+                                    int nslots, int slot_stride, int tgt0, int tgt1, int items, hipStream_t s);
 hipError_t launch_moddown_cols(const DevTables& tb, int log_r, const uint64_t* accp, uint64_t* t2, int tgt0,
                                int tgt1, int items, hipStream_t s);
 hipError_t launch_moddown_blocks(const DevTables& tb, int log_r, const uint64_t* t2, const uint64_t* acc,

@@ -246,12 +246,34 @@ def test_argument_errors(ks):
     G.keyswitch(d, evk, out, 0, ws)
 
 
+def _expected_launches(P, df, c):
+    """Kernel launches of the plan executor: the KeyMult stage starts one
+    kernel for the Q limbs of its target range and one for the P limbs;
+    digit-parallel plans leave the Q limbs to ModDown's last pass."""
+    def chunks(n):
+        return [(n * i // c, n * (i + 1) // c) for i in range(c) if n * i // c < n * (i + 1) // c]
+
+    def km(a, b, q):
+        return int(q and a < min(b, P.ell)) + int(max(a, P.ell) < b)
+    n = 1
+    for a, b in chunks(P.nl):
+        if df in ("DPOB", "DPOC"):
+            n += 1 + km(a, b, False)
+        else:
+            n += P.ndig * (1 + km(a, b, True))
+    return n + 2 * len(chunks(P.ell))
+
+
 def test_launch_counts_follow_table_iii(ks):
-    # launches: DSOB O(d), DPOB O(1), DSOC O(dc), DPOC O(c)
+    # Table III: launches DSOB O(d), DPOB O(1), DSOC O(dc), DPOC O(c)
     G, P = params(ks, 4, 16, 32)
-    d = P.ndig
-    assert G.launch_count(1, ks.make_plan(ks.DPOB)) == 5
-    assert G.launch_count(1, ks.make_plan(ks.DSOB)) == 1 + 2 * d + 2
+    assert G.launch_count(1, ks.make_plan(ks.DPOB)) == 5 == _expected_launches(P, "DPOB", 1)
+    assert G.launch_count(1, ks.make_plan(ks.DSOB)) == _expected_launches(P, "DSOB", 1) == 1 + 3 * P.ndig + 2
     for c in (2, 3, 5):
-        assert G.launch_count(1, ks.make_plan(ks.DPOC, c)) == 1 + 2 * c + 2 * c
-        assert G.launch_count(1, ks.make_plan(ks.DSOC, c)) == 1 + 2 * d * c + 2 * c
+        assert G.launch_count(1, ks.make_plan(ks.DPOC, c)) == _expected_launches(P, "DPOC", c)
+        assert G.launch_count(1, ks.make_plan(ks.DSOC, c)) == _expected_launches(P, "DSOC", c)
+    # scaling: DP plans do not grow with dnum, DS plans do; OC plans grow with chunks
+    G8, P8 = params(ks, 8, 13, 32)
+    assert G8.launch_count(1, ks.make_plan(ks.DPOB)) == G.launch_count(1, ks.make_plan(ks.DPOB))
+    assert G8.launch_count(1, ks.make_plan(ks.DSOB)) > G.launch_count(1, ks.make_plan(ks.DSOB))
+    assert G.launch_count(1, ks.make_plan(ks.DPOC, 6)) > G.launch_count(1, ks.make_plan(ks.DPOC, 3))
