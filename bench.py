@@ -76,7 +76,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--batch", type=int, default=0, help="override the workload's batch size")
-    ap.add_argument("--plan", default="", help="dataflow[,chunks[,log_r]] e.g. DPOB or DSOC,2,3")
+    ap.add_argument("--plan", default="", help="dataflow[,chunks[,log_r[,mfma]]] e.g. DPOB or DSOC,2,3 or DPOB,1,4,mfma")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the library's default plan instead of tuning")
     ap.add_argument("--tune-plans", type=int, default=0, help="candidate plans the tuner times (0 = all)")
@@ -126,7 +126,7 @@ def main():
         df = {"DSOB": ks.DSOB, "DPOB": ks.DPOB, "DSOC": ks.DSOC, "DPOC": ks.DPOC, "STAGED": ks.STAGED}[parts[0]]
         chunks = int(parts[1]) if len(parts) > 1 else 1
         log_r = int(parts[2]) if len(parts) > 2 else -1
-        plan = ks.make_plan(df, chunks, log_r)
+        plan = ks.make_plan(df, chunks, log_r, len(parts) > 3 and parts[3] == "mfma")
 
     to_dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda")
     d = to_dev(ciphertext_batch(G.moduli[:ell], G.n, batch))

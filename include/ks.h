@@ -73,8 +73,18 @@ typedef struct {
   int chunks;   /* output partitions for KS_DSOC / KS_DPOC (1..64), else ignored */
   int log_r;    /* NTT split N = 2^log_r * M: 2^log_r rows per column, blocks of M
                    coefficients (0 = one block pass, up to 5); negative = default */
-  int flags;    /* reserved, must be 0 */
+  int flags;    /* 0 or KS_PLAN_MFMA_BCONV; other bits are rejected (KS_EUNSUP) */
 } ks_plan;
+
+/* Plan flag: run ModUp's and ModDown's fast base conversion (the BConv of
+   the KeySwitch subsection of the Background section, D_j -> PQ \ D_j and
+   P -> Q) as an exact int8 matrix product on the matrix cores: residues and constants are split
+   into balanced signed bytes, the int32 partial sums of each byte weight are
+   folded back modulo the target prime. The output is identical to the
+   default (FP64 / 64-bit integer) BConv. Supported when every digit and P
+   have at most 16 primes and log_r <= 4 (ks_keyswitch returns KS_EUNSUP
+   otherwise). */
+#define KS_PLAN_MFMA_BCONV 1
 
 typedef struct {
   int n, log_n, ell, k, alpha, dnum, ndig;

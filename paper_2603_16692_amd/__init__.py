@@ -27,6 +27,7 @@ KS_MAX_LIMBS = 128
 KS_SET_P = -1
 DSOB, DPOB, DSOC, DPOC, STAGED = 0, 1, 2, 3, 4
 DATAFLOW_NAMES = {DSOB: "DSOB", DPOB: "DPOB", DSOC: "DSOC", DPOC: "DPOC", STAGED: "STAGED"}
+PLAN_MFMA_BCONV = 1  # ks_plan.flags: BConv as an exact int8 product on the matrix cores
 
 
 class Plan(ctypes.Structure):
@@ -34,10 +35,12 @@ class Plan(ctypes.Structure):
                 ("flags", ctypes.c_int)]
 
     def __repr__(self):
-        return f"Plan({DATAFLOW_NAMES.get(self.dataflow, self.dataflow)}, chunks={self.chunks}, log_r={self.log_r})"
+        mx = ", mfma" if self.flags & PLAN_MFMA_BCONV else ""
+        return (f"Plan({DATAFLOW_NAMES.get(self.dataflow, self.dataflow)}, chunks={self.chunks}, "
+                f"log_r={self.log_r}{mx})")
 
     def key(self):
-        return (self.dataflow, self.chunks, self.log_r)
+        return (self.dataflow, self.chunks, self.log_r, self.flags)
 
 
 class Info(ctypes.Structure):
@@ -111,9 +114,10 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def make_plan(dataflow=DPOB, chunks=1, log_r=-1):
-    """A plan; log_r < 0 selects the library's default NTT split."""
-    return Plan(dataflow, chunks, log_r, 0)
+def make_plan(dataflow=DPOB, chunks=1, log_r=-1, mfma=False):
+    """A plan; log_r < 0 selects the library's default NTT split; mfma selects
+    the int8 matrix-core BConv."""
+    return Plan(dataflow, chunks, log_r, PLAN_MFMA_BCONV if mfma else 0)
 
 
 class KsParams:

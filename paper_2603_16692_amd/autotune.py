@@ -42,19 +42,21 @@ def footprint_bytes(dnum: int, n: int, ell: int, dataflow: int, chunks: int = 1,
     return f
 
 
-def candidate_plans(params, batch: int, chunk_range=CHUNK_RANGE):
-    """Every plan libks accepts for these parameters and batch."""
+def candidate_plans(params, batch: int, chunk_range=CHUNK_RANGE, mfma=(False, True)):
+    """Every plan libks accepts for these parameters and batch, with the
+    FP64 / integer BConv and with the int8-MFMA BConv."""
     plans = []
-    for log_r in range(0, 6):
-        log_m = params.log_n - log_r
-        if log_m < 3 or log_m > 14:
-            continue
-        for df in (DSOB, DPOB, STAGED):
-            plans.append(make_plan(df, 1, log_r))
-        for df in (DSOC, DPOC):
-            for c in chunk_range:
-                if c <= params.ell:
-                    plans.append(make_plan(df, c, log_r))
+    for mx in mfma:
+        for log_r in range(0, 6):
+            log_m = params.log_n - log_r
+            if log_m < 3 or log_m > 14:
+                continue
+            for df in (DSOB, DPOB, STAGED):
+                plans.append(make_plan(df, 1, log_r, mx))
+            for df in (DSOC, DPOC):
+                for c in chunk_range:
+                    if c <= params.ell:
+                        plans.append(make_plan(df, c, log_r, mx))
     valid = []
     for p in plans:
         try:
@@ -145,7 +147,7 @@ def tune(params, d, evk, batch: int, plans=None, reps: int = 5, trials: int = 3,
         out.fill_(0)
         ms = time_plan(params, d, evk, out, batch, p, reps, trials)
         exact = bool(torch.equal(out, ref))
-        results.append({"plan": [p.dataflow, p.chunks, p.log_r], "name": repr(p), "ms": ms,
+        results.append({"plan": list(p.key()), "name": repr(p), "ms": ms,
                         "ks_per_s": batch / ms * 1e3, "bit_exact": exact})
         if verbose:
             print(f"  {p!r}: {ms:.4f} ms, {batch / ms * 1e3:.1f} KS/s, bit-exact={exact}", flush=True)
@@ -154,7 +156,7 @@ def tune(params, d, evk, batch: int, plans=None, reps: int = 5, trials: int = 3,
     if best is None:
         raise RuntimeError("no candidate plan reproduced the reference output")
     if cache is not None:
-        cache[_cache_key(params, batch)] = {"plan": [best.dataflow, best.chunks, best.log_r], "ms": best_ms,
+        cache[_cache_key(params, batch)] = {"plan": list(best.key()), "ms": best_ms,
                                              "name": repr(best)}
     return best, results
 
@@ -164,7 +166,8 @@ def cached_plan(params, batch: int, cache: dict):
     e = cache.get(_cache_key(params, batch))
     if not e:
         return None
-    p = make_plan(*e["plan"])
+    df, chunks, log_r = e["plan"][:3]
+    p = make_plan(df, chunks, log_r, bool(e["plan"][3]) if len(e["plan"]) > 3 else False)
     try:
         params.workspace_bytes(batch, p)
     except KsError:
@@ -173,4 +176,4 @@ def cached_plan(params, batch: int, cache: dict):
 
 
 def describe(plan) -> str:
-    return f"{DATAFLOW_NAMES.get(plan.dataflow, plan.dataflow)}(chunks={plan.chunks}, log_r={plan.log_r})"
+    return repr(plan)

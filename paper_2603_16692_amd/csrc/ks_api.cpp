@@ -82,12 +82,13 @@ int resolve_plan(const ks_params* p, const ks_plan* in, ks_plan& out) {
   } else {
     out = ks_plan{KS_DPOB, 1, -1, 0};
   }
-  if (out.flags != 0) return KS_EUNSUP;
+  if (out.flags & ~KS_PLAN_MFMA_BCONV) return KS_EUNSUP;
   if (out.dataflow < KS_DSOB || out.dataflow > KS_STAGED) return KS_EUNSUP;
   if (out.log_r < 0) out.log_r = default_log_r(p->hp.log_n);
   const int log_m = p->hp.log_n - out.log_r;
   if (out.log_r > 5 || log_m < 3 || log_m > 14) return KS_EUNSUP;
   if (ks::stage_cap(p->hp.alpha, out.log_r) == 0 || ks::stage_cap(p->hp.k, out.log_r) == 0) return KS_EUNSUP;
+  if ((out.flags & KS_PLAN_MFMA_BCONV) && !ks::mx_ok(p->tb, out.log_r)) return KS_EUNSUP;
   if (out.dataflow == KS_DSOC || out.dataflow == KS_DPOC) {
     if (out.chunks < 1 || out.chunks > 64 || out.chunks > p->hp.ell) return KS_EUNSUP;
   } else {
@@ -143,8 +144,9 @@ void chunk_range(int n, int c, int i, int& a, int& b) {
 int run_modup(const ks_params* p, const ks_plan& plan, const uint64_t* d, uint64_t* ext, int batch, uint64_t* t1,
               hipStream_t s) {
   const ks::DevTables& tb = p->tb;
+  const int mx = plan.flags & KS_PLAN_MFMA_BCONV;
   KS_TRY(traced(KS_K_INTT_D, s, [&] { return ks::launch_intt_blocks(tb, plan.log_r, d, t1, tb.ell, batch, s); }));
-  KS_TRY(traced(KS_K_MODUP_COLS, s, [&] { return ks::launch_modup_cols(tb, plan.log_r, t1, ext, 0, tb.ndig, tb.ndig, 1, 0, tb.nl, batch, s); }));
+  KS_TRY(traced(KS_K_MODUP_COLS, s, [&] { return ks::launch_modup_cols(tb, plan.log_r, t1, ext, 0, tb.ndig, tb.ndig, 1, 0, tb.nl, batch, mx, s); }));
   KS_TRY(traced(KS_K_EXT_BLOCKS, s, [&] { return ks::launch_ext_blocks(tb, plan.log_r, ext, batch, s); }));
   KS_TRY(traced(KS_K_COPY_DIGITS, s, [&] { return ks::launch_copy_digits(tb, d, ext, batch, s); }));
   return KS_OK;
@@ -153,8 +155,9 @@ int run_modup(const ks_params* p, const ks_plan& plan, const uint64_t* d, uint64
 int run_moddown(const ks_params* p, const ks_plan& plan, const uint64_t* acc, uint64_t* out, int batch,
                 uint64_t* accp, uint64_t* t2, hipStream_t s) {
   const ks::DevTables& tb = p->tb;
+  const int mx = plan.flags & KS_PLAN_MFMA_BCONV;
   KS_TRY(traced(KS_K_PBLOCKS_INV, s, [&] { return ks::launch_pblocks_inv(tb, plan.log_r, acc, accp, batch, s); }));
-  KS_TRY(traced(KS_K_MODDOWN_COLS, s, [&] { return ks::launch_moddown_cols(tb, plan.log_r, accp, t2, 0, tb.ell, batch, s); }));
+  KS_TRY(traced(KS_K_MODDOWN_COLS, s, [&] { return ks::launch_moddown_cols(tb, plan.log_r, accp, t2, 0, tb.ell, batch, mx, s); }));
   KS_TRY(traced(KS_K_MODDOWN_BLOCKS, s, [&] { return ks::launch_moddown_blocks(tb, plan.log_r, t2, acc, out, 0, tb.ell, batch, s); }));
   return KS_OK;
 }
@@ -179,6 +182,7 @@ int run_fused(const ks_params* p, const ks_plan& plan, const uint64_t* d, const 
   uint64_t* acc = reinterpret_cast<uint64_t*>(ws + L.acc);
   uint64_t* t2 = reinterpret_cast<uint64_t*>(ws + L.t2);
   const bool dp = plan.dataflow == KS_DPOB || plan.dataflow == KS_DPOC;
+  const int mx = plan.flags & KS_PLAN_MFMA_BCONV;
   const int c = plan.chunks;
   int count = 0;
   const bool run = launches == nullptr;
@@ -191,7 +195,7 @@ int run_fused(const ks_params* p, const ks_plan& plan, const uint64_t* d, const 
     if (dp) {
       if (run) {
         KS_TRY(traced(KS_K_MODUP_COLS, s, [&] {
-          return ks::launch_modup_cols(tb, plan.log_r, t1, ext1, 0, tb.ndig, L.nslots, 1, a, b, batch, s);
+          return ks::launch_modup_cols(tb, plan.log_r, t1, ext1, 0, tb.ndig, L.nslots, 1, a, b, batch, mx, s);
         }));
         if (km_kernels(tb, a, b, false))
           KS_TRY(traced(KS_K_KEYMULT_BLOCKS, s, [&] {
@@ -204,7 +208,7 @@ int run_fused(const ks_params* p, const ks_plan& plan, const uint64_t* d, const 
       for (int j = 0; j < tb.ndig; ++j) {
         if (run) {
           KS_TRY(traced(KS_K_MODUP_COLS, s, [&] {
-            return ks::launch_modup_cols(tb, plan.log_r, t1, ext1, j, 1, 1, 0, a, b, batch, s);
+            return ks::launch_modup_cols(tb, plan.log_r, t1, ext1, j, 1, 1, 0, a, b, batch, mx, s);
           }));
           KS_TRY(traced(KS_K_KEYMULT_BLOCKS, s, [&] {
             return ks::launch_keymult_blocks(tb, plan.log_r, d, ext1, evk, acc, j, j + 1, 1, 0, a, b, batch, j > 0,
@@ -220,7 +224,7 @@ int run_fused(const ks_params* p, const ks_plan& plan, const uint64_t* d, const 
     chunk_range(tb.ell, c, ci, a, b);
     if (a == b) continue;
     if (run) {
-      KS_TRY(traced(KS_K_MODDOWN_COLS, s, [&] { return ks::launch_moddown_cols(tb, plan.log_r, acc, t2, a, b, batch, s); }));
+      KS_TRY(traced(KS_K_MODDOWN_COLS, s, [&] { return ks::launch_moddown_cols(tb, plan.log_r, acc, t2, a, b, batch, mx, s); }));
       if (dp)
         KS_TRY(traced(KS_K_MODDOWN_BLOCKS, s, [&] {
           return ks::launch_moddown_km_blocks(tb, plan.log_r, d, ext1, evk, t2, out, 0, tb.ndig, L.nslots, 1, a, b,
@@ -277,6 +281,8 @@ int ks_params_create(int dnum, int log_n, int ell, ks_params** out) {
   rebase(p->tb.dn_pinv);
   rebase(p->tb.up_hinv);
   rebase(p->tb.dn_hinv);
+  rebase(p->tb.up_mx);
+  rebase(p->tb.dn_mx);
   rebase(p->tb.twf_d);
   rebase(p->tb.twi_d);
   rebase(p->tb.up_pre_d);

@@ -35,6 +35,10 @@ struct LimbC {
   double qinv;         // fl(1 / q)
   double ninv_d;       // balanced N^-1 mod q (Q primes)
   uint64_t r64, r64_s; // 2^64 mod q with its Shoup companion
+  // Recombination of the int8-MFMA base conversion (see k_modup_cols_mx):
+  double r32_d;        // balanced 2^32 mod q (Q primes)
+  uint64_t r32, r32_s; // 2^32 mod q with its Shoup companion (P primes)
+  uint64_t cadj;       // (-2^51 - 2^83) mod q (P primes)
 };
 
 // Every table of one parameter set. Pointers are device addresses after
@@ -57,6 +61,11 @@ struct DevTables {
   const double* dn_pinv_d;  // [ell]: balanced [P^-1]_{q_i}
   const uint64_t* up_hinv;  // [ell][2]: [(D_j/q_i)^-1]_{q_i}, Shoup (no N^-1)
   const uint64_t* dn_hinv;  // [k][2]: [(P/p_m)^-1]_{p_m}, Shoup (no N^-1)
+  // Constant operands of the int8-MFMA base conversion: per 4-target group
+  // and MFMA step, 16 bytes per lane (see k_modup_cols_mx for the layout).
+  const uint64_t* up_mx;    // [ndig][up_ng][up_nm][64][2]
+  const uint64_t* dn_mx;    // [dn_ng][dn_nm][64][2]
+  int up_ng, up_nm, dn_ng, dn_nm;
 };
 
 // ------------------------------------------------------------ integers

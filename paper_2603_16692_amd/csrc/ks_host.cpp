@@ -96,6 +96,52 @@ uint64_t mont_neg_inv(uint64_t q) {
 
 size_t align_words(size_t w) { return (w + 31) & ~(size_t)31; }
 
+// Balanced base-256 digits of v < 2^60: v = sum_b d_b 256^b with d_b in
+// [-128, 127] for b < 7 and 0 <= d_7 < 18. Adding 128 to each of the seven
+// low bytes turns them into the unsigned bytes of z = v + 0x0080...80, whose
+// carries propagate exactly as in the digit recurrence.
+void balanced_digits(uint64_t v, int8_t d[8]) {
+  const uint64_t z = v + 0x0080808080808080ull;
+  for (int b = 0; b < 7; ++b) d[b] = (int8_t)((int)((z >> (8 * b)) & 0xFF) - 128);
+  d[7] = (int8_t)(z >> 56);
+}
+
+// Row rho of a 32-row MFMA tile holds byte b of target tau of the group
+// (see k_modup_cols_mx): rho = 8*g8 + 4*hh + e with tau = 2*hh + g8/2 and
+// b = 4*(g8%2) + e, so that accumulator i of a lane in half hh of the
+// wavefront holds byte i%8 of target 2*hh + i/8.
+void row_target_byte(int rho, int& tau, int& b) {
+  const int g8 = rho >> 3, hh = (rho >> 2) & 1, e = rho & 3;
+  tau = 2 * hh + (g8 >> 1);
+  b = 4 * (g8 & 1) + e;
+}
+
+// 16 constant bytes of lane l, MFMA step m, for sources 4m + 2*(l/32) + w
+// (w = 0, 1; source index s in [0, nsrc)) and row l%32. cst(s, tau) returns
+// the BConv constant c_{s,t} and its modulus (modulus 0 = no such target).
+template <class Cst>
+void mx_lane(uint64_t* out, int l, int m, int nsrc, Cst cst) {
+  int tau, b;
+  row_target_byte(l & 31, tau, b);
+  for (int w = 0; w < 2; ++w) {
+    const int s = 4 * m + 2 * (l >> 5) + w;
+    uint64_t word = 0;
+    uint64_t c = 0, mod = 0;
+    if (s < nsrc) cst(s, tau, c, mod);
+    if (mod) {
+      // byte a of the word: digit b of [c * 256^a]_mod
+      uint64_t ca = c;
+      for (int a = 0; a < 8; ++a) {
+        int8_t dg[8];
+        balanced_digits(ca, dg);
+        word |= (uint64_t)(uint8_t)dg[b] << (8 * a);
+        ca = host_mulmod(ca, 256, mod);
+      }
+    }
+    out[w] = word;
+  }
+}
+
 }  // namespace
 
 bool derive_params(int dnum, int log_n, int ell, HostParams& hp) {
@@ -141,6 +187,18 @@ void build_tables(const HostParams& hp, std::vector<uint64_t>& blob, DevTables& 
   const size_t o_up_mat_d = take((size_t)ell * ell);
   const size_t o_dn_mat_d = take((size_t)k * ell * 2);
   const size_t o_dn_pinv_d = take((size_t)ell);
+  // MFMA BConv groups: per digit, the Q targets outside the digit in groups
+  // of four, then the P targets in groups of four.
+  const int alpha = hp.alpha, ndig = hp.ndig;
+  const int npg = (k + 3) / 4;
+  int up_ng = 0;
+  for (int j = 0; j < ndig; ++j) {
+    const int na = std::min(alpha, ell - j * alpha);
+    up_ng = std::max(up_ng, (ell - na + 3) / 4 + npg);
+  }
+  const int up_nm = (alpha + 3) / 4, dn_ng = (ell + 3) / 4, dn_nm = (k + 3) / 4;
+  const size_t o_up_mx = take((size_t)ndig * up_ng * up_nm * 128);
+  const size_t o_dn_mx = take((size_t)dn_ng * dn_nm * 128);
   blob.assign(off, 0);
   // balanced representative of a residue as a double (Q primes only)
   auto bal = [](uint64_t v, uint64_t q) {
@@ -168,6 +226,16 @@ void build_tables(const HostParams& hp, std::vector<uint64_t>& blob, DevTables& 
     L.red_s = shoup(1, q);
     L.r64 = (uint64_t)(((u128)1 << 64) % q);
     L.r64_s = shoup(L.r64, q);
+    L.r32 = ((uint64_t)1 << 32) % q;
+    L.r32_s = shoup(L.r32, q);
+    {
+      uint64_t b = bal(L.r32, q);
+      std::memcpy(&L.r32_d, &b, sizeof(b));
+    }
+    // -(2^51 + 2^83) mod q
+    const uint64_t c51 = ((uint64_t)1 << 51) % q;
+    const uint64_t c83 = (uint64_t)(((u128)1 << 83) % q);
+    L.cadj = (2 * q - c51 - c83) % q;
     L.qd = (double)q;
     L.qinv = 1.0 / (double)q;
     {
@@ -246,6 +314,41 @@ void build_tables(const HostParams& hp, std::vector<uint64_t>& blob, DevTables& 
     blob[o_dn_pinv_d + i] = bal(pinv, qi);
   }
 
+  // MFMA BConv constant operands
+  for (int j = 0; j < ndig; ++j) {
+    const int lo = j * alpha, na = std::min(alpha, ell - lo);
+    const int nq = ell - na, nqg = (nq + 3) / 4;
+    for (int g = 0; g < nqg + npg; ++g)
+      for (int m = 0; m < up_nm; ++m)
+        for (int l = 0; l < 64; ++l) {
+          uint64_t* dst = &blob[o_up_mx + ((((size_t)j * up_ng + g) * up_nm + m) * 64 + l) * 2];
+          mx_lane(dst, l, m, na, [&](int sidx, int tau, uint64_t& c, uint64_t& mod) {
+            int t = -1;
+            if (g < nqg) {
+              const int u = 4 * g + tau;
+              if (u < nq) t = u < lo ? u : u + na;
+            } else {
+              const int v = 4 * (g - nqg) + tau;
+              if (v < k) t = ell + v;
+            }
+            if (t < 0) return;
+            c = blob[o_up_mat + ((size_t)(lo + sidx) * nl + t) * 2];
+            mod = hp.mod[t];
+          });
+        }
+  }
+  for (int g = 0; g < dn_ng; ++g)
+    for (int m = 0; m < dn_nm; ++m)
+      for (int l = 0; l < 64; ++l) {
+        uint64_t* dst = &blob[o_dn_mx + (((size_t)g * dn_nm + m) * 64 + l) * 2];
+        mx_lane(dst, l, m, k, [&](int sidx, int tau, uint64_t& c, uint64_t& mod) {
+          const int t = 4 * g + tau;
+          if (t >= ell) return;
+          c = blob[o_dn_mat + ((size_t)sidx * ell + t) * 2];
+          mod = hp.mod[t];
+        });
+      }
+
   tb.log_n = hp.log_n;
   tb.ell = ell;
   tb.k = k;
@@ -263,6 +366,12 @@ void build_tables(const HostParams& hp, std::vector<uint64_t>& blob, DevTables& 
   tb.dn_pinv = at(o_dn_pinv);
   tb.up_hinv = at(o_up_hinv);
   tb.dn_hinv = at(o_dn_hinv);
+  tb.up_mx = at(o_up_mx);
+  tb.dn_mx = at(o_dn_mx);
+  tb.up_ng = up_ng;
+  tb.up_nm = up_nm;
+  tb.dn_ng = dn_ng;
+  tb.dn_nm = dn_nm;
   auto atd = [](size_t o) { return reinterpret_cast<const double*>(o * sizeof(uint64_t)); };
   tb.twf_d = atd(o_twf_d);
   tb.twi_d = atd(o_twi_d);

@@ -270,6 +270,225 @@ __global__ __launch_bounds__(CT, LOGR <= 4 ? 4 : 2) void k_modup_cols(DevTables 
   }
 }
 
+// ------------------------------------------- int8-MFMA base conversion
+
+// BConv as an exact integer contraction on the matrix cores. Each residue
+// y < 2^60 is written in balanced base-256 digits y = sum_a d_a 256^a
+// (d_a in [-128, 127], signed bytes), and each constant c_{s,t} is folded
+// with the digit weight, c'_{s,a,t} = [c_{s,t} 256^a]_t, and split the same
+// way into bytes e_{s,a,t,b}. Then
+//   sum_s y_s c_{s,t} = sum_b 256^b C_b  (mod t),  C_b = sum_{s,a} d_{s,a} e_{s,a,t,b},
+// and every C_b is one entry of an int8 x int8 -> int32 matrix product with
+// K = 8 * (number of sources): rows (t, b) come from the constant table,
+// columns are coefficients. |C_b| <= 8 * 16 * 128 * 128 = 2^21 for up to 16
+// sources. A 32-row tile covers four targets; the host's row order puts all
+// eight C_b of targets 2h and 2h+1 in the accumulators of lane half h
+// (accumulator i = byte i % 8 of target 2h + i / 8).
+// MFMA v_mfma_i32_32x32x32_i8: lane l supplies 16 bytes of row (or column)
+// l % 32 at K offsets 16 * (l / 32) .. +15, i.e. sources 4m + 2(l/32) + {0, 1}
+// of step m, eight digit bytes each.
+typedef int mx_v4i __attribute__((ext_vector_type(4)));
+typedef int mx_v16i __attribute__((ext_vector_type(16)));
+
+// Signed bytes of the balanced digits of v < 2^60 (byte 7 is below 18):
+// adding 128 to each of the seven low bytes makes them the unsigned bytes of
+// v + 0x0080...80; flipping their top bit subtracts the 128 again modulo 256.
+__device__ __forceinline__ uint64_t mx_pack(uint64_t v) {
+  return (v + 0x0080808080808080ull) ^ 0x0080808080808080ull;
+}
+
+__device__ __forceinline__ mx_v16i mx_step(const ulonglong2& a, const ulonglong2& b, const mx_v16i& acc) {
+  const mx_v4i av = {(int)(uint32_t)a.x, (int)(uint32_t)(a.x >> 32), (int)(uint32_t)a.y, (int)(uint32_t)(a.y >> 32)};
+  const mx_v4i bv = {(int)(uint32_t)b.x, (int)(uint32_t)(b.x >> 32), (int)(uint32_t)b.y, (int)(uint32_t)(b.y >> 32)};
+  return __builtin_amdgcn_mfma_i32_32x32x32_i8(av, bv, acc, 0, 0, 0);
+}
+
+// The target whose partial sums start at accumulator BASE (0 or 8), as
+// lo = C0 + 2^8 C1 + 2^16 C2 + 2^24 C3 and hi = C4 + ... + 2^24 C7, exact
+// doubles below 2^46.1 in magnitude (the sum is lo + 2^32 hi).
+template <int BASE>
+__device__ __forceinline__ void mx_halves(const mx_v16i& acc, double& lo, double& hi) {
+  const int a0 = acc[BASE + 0] + acc[BASE + 1] * 256, a1 = acc[BASE + 2] + acc[BASE + 3] * 256;
+  const int b0 = acc[BASE + 4] + acc[BASE + 5] * 256, b1 = acc[BASE + 6] + acc[BASE + 7] * 256;
+  lo = __fma_rn((double)a1, 65536.0, (double)a0);
+  hi = __fma_rn((double)b1, 65536.0, (double)b0);
+}
+
+// lo + 2^32 hi mod q for a Q prime: |result| <= q/2 + 1.
+__device__ __forceinline__ double mx_fold_q(double lo, double hi, double q, double qinv, double r32) {
+  return f_red(lo + f_mul(hi, r32, q, qinv), q, qinv);
+}
+
+// lo + 2^32 hi mod p for a P prime, in [0, 4p): with u = x + 2^51 >= 0 read
+// from the mantissa of x + 1.5 * 2^52, the value is
+// u_lo + 2^32 u_hi - 2^51 - 2^83, and cadj = (-2^51 - 2^83) mod p.
+__device__ __forceinline__ uint64_t mx_fold_p(double lo, double hi, const LimbC& L) {
+  const uint64_t ul = (uint64_t)__double_as_longlong(lo + 6755399441055744.0) & 0x000FFFFFFFFFFFFFull;
+  const uint64_t uh = (uint64_t)__double_as_longlong(hi + 6755399441055744.0) & 0x000FFFFFFFFFFFFFull;
+  return ul + mul_shoup(uh, L.r32, L.r32_s, L.q) + L.cadj;
+}
+
+// Phase 2 of the MFMA column kernels for one target group: for each row r,
+// nm MFMA steps over the packed digits yp ([pairs][R][64] x 16 bytes) give
+// the partial sums of targets ta (lane half 0: 2h, ...) and tb2; fold, run
+// the forward column pass and store the rows of each target whose store flag
+// is set. Q groups store canonical residues, P groups [0, 4p).
+template <int LOGR, bool QG>
+__device__ __forceinline__ void mx_group(const DevTables& tb, const ulonglong2* yp, const ulonglong2* cst_g, int nm,
+                                         int ta, int tb2, bool sa, bool sb, uint64_t* oa, uint64_t* ob, size_t cc,
+                                         int M) {
+  constexpr int R = 1 << LOGR;
+  const int lane = threadIdx.x & (TC - 1), h = lane >> 5;
+  const int ycol = ((threadIdx.x / TC) & 1) * 32 + (lane & 31);
+  ulonglong2 cst[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+    if (m < nm) cst[m] = cst_g[m * 64 + lane];
+  const LimbC& La = tb.limb[ta];
+  const LimbC& Lb = tb.limb[tb2];
+  const size_t N = (size_t)M * R;
+  if constexpr (QG) {
+    const double qa = La.qd, qia = La.qinv, ra = La.r32_d;
+    const double qb = Lb.qd, qib = Lb.qinv, rb = Lb.r32_d;
+    double za[R], zb[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      mx_v16i acc = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        if (m < nm) acc = mx_step(cst[m], yp[((2 * m + h) * R + r) * TC + ycol], acc);
+      double l0, h0, l1, h1;
+      mx_halves<0>(acc, l0, h0);
+      mx_halves<8>(acc, l1, h1);
+      za[r] = mx_fold_q(l0, h0, qa, qia, ra);
+      zb[r] = mx_fold_q(l1, h1, qb, qib, rb);
+      // Materialise this row's results here, so that the compiler does not
+      // sink the folds below the loop and keep all rows' accumulators live.
+      asm volatile("" : "+v"(za[r]), "+v"(zb[r]));
+    }
+    sub_fwd<LOGR>(ArF{qa, qia, tb.twf_d + (size_t)ta * N}, za, 1u);
+    if (sa) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) oa[cc + (size_t)r * M] = f_canon(za[r], qa, qia);
+    }
+    sub_fwd<LOGR>(ArF{qb, qib, tb.twf_d + (size_t)tb2 * N}, zb, 1u);
+    if (sb) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) ob[cc + (size_t)r * M] = f_canon(zb[r], qb, qib);
+    }
+  } else {
+    uint64_t za[R], zb[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      mx_v16i acc = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        if (m < nm) acc = mx_step(cst[m], yp[((2 * m + h) * R + r) * TC + ycol], acc);
+      double l0, h0, l1, h1;
+      mx_halves<0>(acc, l0, h0);
+      mx_halves<8>(acc, l1, h1);
+      za[r] = mx_fold_p(l0, h0, La);
+      zb[r] = mx_fold_p(l1, h1, Lb);
+      asm volatile("" : "+v"(za[r]), "+v"(zb[r]));
+    }
+    sub_fwd<LOGR>(ArI{La.q, La.two_q, tb.twf + (size_t)ta * N * 2}, za, 1u);
+    if (sa) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) oa[cc + (size_t)r * M] = za[r];
+    }
+    sub_fwd<LOGR>(ArI{Lb.q, Lb.two_q, tb.twf + (size_t)tb2 * N * 2}, zb, 1u);
+    if (sb) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) ob[cc + (size_t)r * M] = zb[r];
+    }
+  }
+}
+
+// ModUp columns with the int8-MFMA BConv: same arguments and output as
+// k_modup_cols. Phase 1 (wave w: sources w, w + 8, ... < 4 nm): inverse
+// column pass and pre-scale as in k_modup_cols, canonical y packed into LDS
+// as [pair][R][64] x 16 bytes (pair p = sources 2p, 2p + 1; zero past the
+// digit's sources and for columns past M). Phase 2: wave w takes the column
+// half w % 2 (lane l works on column (w % 2) * 32 + l % 32 of the workgroup)
+// and the target groups w/2, w/2 + 4, ...: per digit the Q targets outside
+// D_j in groups of four (in basis order), then the P targets.
+template <int LOGR>
+__global__ __launch_bounds__(CT) void k_modup_cols_mx(DevTables tb, const uint64_t* t1, uint64_t* ext1, int j0,
+                                                     int nslots, int slot_stride, int tgt0, int tgt1, int log_m) {
+  constexpr int R = 1 << LOGR;
+  extern __shared__ ulonglong2 yp[];
+  const int M = 1 << log_m;
+  const size_t N = (size_t)M * R;
+  const int lane = threadIdx.x & (TC - 1), wv = threadIdx.x / TC;
+  const size_t c = (size_t)blockIdx.x * TC + lane;
+  const bool live = c < (size_t)M;
+  const int j = j0 + blockIdx.y;
+  const int item = blockIdx.z;
+  const int ell = tb.ell, nl = tb.nl, k = tb.k;
+  const int lo = j * tb.alpha;
+  const int na = min(lo + tb.alpha, ell) - lo;
+  const int nm = tb.up_nm;
+  uint64_t* yw = reinterpret_cast<uint64_t*>(yp);
+  for (int s = wv; s < 4 * nm; s += CW) {
+    uint64_t y[R];
+    if (live && s < na) {
+      const int i = lo + s;
+      const LimbC L = tb.limb[i];
+      const uint64_t* a = t1 + ((size_t)item * ell + i) * N;
+      double v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = u2d(a[c + (size_t)r * M]);
+      sub_inv<LOGR>(arf(tb, L, i, true), v, 1u);
+      const double w = tb.up_pre_d[i];
+#pragma unroll
+      for (int r = 0; r < R; ++r) y[r] = mx_pack(d2u(f_canon_d(f_mul(v[r], w, L.qd, L.qinv), L.qd, L.qinv)));
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) y[r] = 0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) yw[((size_t)((s >> 1) * R + r) * TC + lane) * 2 + (s & 1)] = y[r];
+  }
+  __syncthreads();
+  const int h = lane >> 5;
+  const size_t cc = (size_t)blockIdx.x * TC + (wv & 1) * 32 + (lane & 31);
+  const bool clive = cc < (size_t)M;
+  const int slot = slot_stride ? j : 0;
+  uint64_t* e = ext1 + ((size_t)item * nslots + slot) * (size_t)nl * N;
+  const int nq = ell - na, nqg = (nq + 3) >> 2, ng = nqg + ((k + 3) >> 2);
+  const ulonglong2* cst_j = reinterpret_cast<const ulonglong2*>(tb.up_mx) + (size_t)j * tb.up_ng * nm * 64;
+  for (int g = wv >> 1; g < ng; g += CW / 2) {
+    const bool qg = g < nqg;
+    int tg[4];
+    bool any = false;
+#pragma unroll
+    for (int tau = 0; tau < 4; ++tau) {
+      int t = -1;
+      if (qg) {
+        const int u = 4 * g + tau;
+        if (u < nq) t = u < lo ? u : u + na;
+      } else {
+        const int v = 4 * (g - nqg) + tau;
+        if (v < k) t = ell + v;
+      }
+      tg[tau] = t;
+      any = any || (t >= tgt0 && t < tgt1);
+    }
+    if (!any) continue;
+    const int ta = tg[2 * h], tb2 = tg[2 * h + 1];
+    const bool sa = clive && ta >= tgt0 && ta < tgt1;
+    const bool sb = clive && tb2 >= tgt0 && tb2 < tgt1;
+    const int pad = qg ? 0 : ell;  // stand-in limb for padding slots (never stored)
+    const int la = ta >= 0 ? ta : pad, lb = tb2 >= 0 ? tb2 : pad;
+    if (qg)
+      mx_group<LOGR, true>(tb, yp, cst_j + (size_t)g * nm * 64, nm, la, lb, sa, sb, e + (size_t)la * N,
+                           e + (size_t)lb * N, cc, M);
+    else
+      mx_group<LOGR, false>(tb, yp, cst_j + (size_t)g * nm * 64, nm, la, lb, sa, sb, e + (size_t)la * N,
+                            e + (size_t)lb * N, cc, M);
+  }
+}
+
 // ---------------------------------------------------------- KeyMult (K3)
 
 // One block b of one target limb t in [tgt0, tgt0 + ntgt) of one item per
@@ -467,6 +686,62 @@ __global__ __launch_bounds__(CT, LOGR <= 4 ? 4 : 2) void k_moddown_cols(DevTable
     uint64_t* o = t2 + (((size_t)item * 2 + comp) * ell + i) * N;
 #pragma unroll
     for (int r = 0; r < R; ++r) o[c + (size_t)r * M] = f_canon(z[r], L.qd, L.qinv);
+  }
+}
+
+// ModDown columns with the int8-MFMA BConv: same arguments and output as
+// k_moddown_cols. Phase 1 (wave w: P limbs w, w + 8, ... < 4 nm): inverse
+// column pass of acc_P and the scale by N^-1 [(P/p_m)^-1]_{p_m} as in
+// k_moddown_cols, canonical y packed into LDS ([pair][R][64] x 16 bytes,
+// zero past the k sources and for columns past M). Phase 2: wave w takes the
+// column half w % 2 and the groups of four Q limbs w/2, w/2 + 4, ... that
+// meet [tgt0, tgt1); output t2 canonical.
+template <int LOGR>
+__global__ __launch_bounds__(CT) void k_moddown_cols_mx(DevTables tb, const uint64_t* accp, uint64_t* t2, int tgt0,
+                                                       int tgt1, int log_m) {
+  constexpr int R = 1 << LOGR;
+  extern __shared__ ulonglong2 yp[];
+  const int M = 1 << log_m;
+  const size_t N = (size_t)M * R;
+  const int lane = threadIdx.x & (TC - 1), wv = threadIdx.x / TC;
+  const size_t c = (size_t)blockIdx.x * TC + lane;
+  const bool live = c < (size_t)M;
+  const int comp = blockIdx.y, item = blockIdx.z;
+  const int ell = tb.ell, nl = tb.nl, k = tb.k;
+  const int nm = tb.dn_nm;
+  uint64_t* yw = reinterpret_cast<uint64_t*>(yp);
+  for (int m = wv; m < 4 * nm; m += CW) {
+    uint64_t y[R];
+    if (live && m < k) {
+      const LimbC L = tb.limb[ell + m];
+      const uint64_t* a = accp + (((size_t)item * 2 + comp) * nl + ell + m) * N;
+#pragma unroll
+      for (int r = 0; r < R; ++r) y[r] = a[c + (size_t)r * M];
+      sub_inv<LOGR>(ari(tb, L, ell + m, true), y, 1u);
+      const uint64_t w = tb.dn_pre[2 * m], ws = tb.dn_pre[2 * m + 1];
+#pragma unroll
+      for (int r = 0; r < R; ++r) y[r] = mx_pack(reduce2(mul_shoup(y[r], w, ws, L.q), L.q));
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) y[r] = 0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) yw[((size_t)((m >> 1) * R + r) * TC + lane) * 2 + (m & 1)] = y[r];
+  }
+  __syncthreads();
+  const int h = lane >> 5;
+  const size_t cc = (size_t)blockIdx.x * TC + (wv & 1) * 32 + (lane & 31);
+  const bool clive = cc < (size_t)M;
+  uint64_t* o = t2 + ((size_t)item * 2 + comp) * ell * N;
+  const ulonglong2* cst = reinterpret_cast<const ulonglong2*>(tb.dn_mx);
+  for (int g = (wv >> 1) + ((tgt0 >> 2) & ~(CW / 2 - 1)); 4 * g < tgt1; g += CW / 2) {
+    if (4 * g + 4 <= tgt0) continue;
+    const int ta = 4 * g + 2 * h, tb2 = ta + 1;
+    const bool sa = clive && ta >= tgt0 && ta < tgt1;
+    const bool sb = clive && tb2 >= tgt0 && tb2 < tgt1;
+    const int la = ta < ell ? ta : 0, lb = tb2 < ell ? tb2 : 0;
+    mx_group<LOGR, true>(tb, yp, cst + (size_t)g * nm * 64, nm, la, lb, sa, sb, o + (size_t)la * N,
+                         o + (size_t)lb * N, cc, M);
   }
 }
 
@@ -709,6 +984,9 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_pblocks_inv(DevTables 
 
 // ------------------------------------------------------------ dispatching
 
+// LDS of an MFMA column workgroup: 2 nm pairs of 16-byte digit words per row and column.
+inline size_t mx_lds_bytes(int nm, int log_r) { return (size_t)nm * ((size_t)1 << log_r) * TC * 32; }
+
 template <template <int> class F, typename... A>
 hipError_t by_logr(int log_r, A... a) {
   switch (log_r) {
@@ -718,6 +996,19 @@ hipError_t by_logr(int log_r, A... a) {
     case 3: return F<3>::run(a...);
     case 4: return F<4>::run(a...);
     case 5: return F<5>::run(a...);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// The MFMA column kernels hold 2R values per lane: at most 16 rows.
+template <template <int> class F, typename... A>
+hipError_t by_logr_mx(int log_r, A... a) {
+  switch (log_r) {
+    case 0: return F<0>::run(a...);
+    case 1: return F<1>::run(a...);
+    case 2: return F<2>::run(a...);
+    case 3: return F<3>::run(a...);
+    case 4: return F<4>::run(a...);
     default: return hipErrorInvalidValue;
   }
 }
@@ -818,6 +1109,17 @@ struct ModupCols {
     return hipGetLastError();
   }
 };
+template <int LOGR>
+struct ModupColsMx {
+  static hipError_t run(const DevTables& tb, const uint64_t* t1, uint64_t* ext1, int j0, int nj, int nslots,
+                        int slot_stride, int tgt0, int tgt1, int items, int log_m, hipStream_t s) {
+    allow_lds<k_modup_cols_mx<LOGR>>();
+    const size_t lds = mx_lds_bytes(tb.up_nm, LOGR);
+    k_modup_cols_mx<LOGR><<<col_grid(log_m, nj, items), dim3(CT), lds, s>>>(tb, t1, ext1, j0, nslots, slot_stride,
+                                                                            tgt0, tgt1, log_m);
+    return hipGetLastError();
+  }
+};
 template <int LOGM, int LOGE>
 struct KeymultBlocks {
   static hipError_t run(const DevTables& tb, const uint64_t* d, const uint64_t* ext1, const uint64_t* evk,
@@ -852,6 +1154,16 @@ struct ModdownCols {
     allow_lds<k_moddown_cols<LOGR>>();
     const size_t lds = sizeof(uint64_t) * (size_t)tb.k * (1 << LOGR) * TC;
     k_moddown_cols<LOGR><<<col_grid(log_m, 2, items), dim3(CT), lds, s>>>(tb, accp, t2, tgt0, tgt1, log_m);
+    return hipGetLastError();
+  }
+};
+template <int LOGR>
+struct ModdownColsMx {
+  static hipError_t run(const DevTables& tb, const uint64_t* accp, uint64_t* t2, int tgt0, int tgt1, int items,
+                        int log_m, hipStream_t s) {
+    allow_lds<k_moddown_cols_mx<LOGR>>();
+    const size_t lds = mx_lds_bytes(tb.dn_nm, LOGR);
+    k_moddown_cols_mx<LOGR><<<col_grid(log_m, 2, items), dim3(CT), lds, s>>>(tb, accp, t2, tgt0, tgt1, log_m);
     return hipGetLastError();
   }
 };
@@ -908,6 +1220,12 @@ struct PBlocksInv {
 // columns per workgroup, 8 bytes each, at most 160 KB).
 int stage_cap(int count, int log_r) { return (size_t)count * ((size_t)1 << log_r) * 64 * 8 <= 160 * 1024 ? 1 : 0; }
 
+int mx_ok(const DevTables& tb, int log_r) {
+  // at most 16 sources (the partial-sum bound), 16 rows per column (registers), LDS
+  return tb.up_nm <= 4 && tb.dn_nm <= 4 && log_r <= 4 && mx_lds_bytes(tb.up_nm, log_r) <= 160 * 1024 &&
+         mx_lds_bytes(tb.dn_nm, log_r) <= 160 * 1024;
+}
+
 hipError_t launch_ntt(const DevTables& tb, int log_r, uint64_t* x, int first, int nlimbs, int items, hipStream_t s) {
   const int log_m = tb.log_n - log_r;
   hipError_t e = hipSuccess;
@@ -929,7 +1247,10 @@ hipError_t launch_intt_blocks(const DevTables& tb, int log_r, const uint64_t* sr
 }
 
 hipError_t launch_modup_cols(const DevTables& tb, int log_r, const uint64_t* t1, uint64_t* ext1, int j0, int nj,
-                             int nslots, int slot_stride, int tgt0, int tgt1, int items, hipStream_t s) {
+                             int nslots, int slot_stride, int tgt0, int tgt1, int items, int mfma, hipStream_t s) {
+  if (mfma)
+    return by_logr_mx<ModupColsMx>(log_r, tb, t1, ext1, j0, nj, nslots, slot_stride, tgt0, tgt1, items,
+                                tb.log_n - log_r, s);
   return by_logr<ModupCols>(log_r, tb, t1, ext1, j0, nj, nslots, slot_stride, tgt0, tgt1, items, tb.log_n - log_r, s);
 }
 
@@ -949,7 +1270,8 @@ hipError_t launch_moddown_km_blocks(const DevTables& tb, int log_r, const uint64
 }
 
 hipError_t launch_moddown_cols(const DevTables& tb, int log_r, const uint64_t* accp, uint64_t* t2, int tgt0,
-                               int tgt1, int items, hipStream_t s) {
+                               int tgt1, int items, int mfma, hipStream_t s) {
+  if (mfma) return by_logr_mx<ModdownColsMx>(log_r, tb, accp, t2, tgt0, tgt1, items, tb.log_n - log_r, s);
   return by_logr<ModdownCols>(log_r, tb, accp, t2, tgt0, tgt1, items, tb.log_n - log_r, s);
 }
 

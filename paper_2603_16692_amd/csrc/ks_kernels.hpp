@@ -12,6 +12,9 @@ namespace ks {
 // Nonzero when the column kernels can stage `count` source limbs of 2^log_r
 // rows each in LDS.
 int stage_cap(int count, int log_r);
+// Nonzero when the int8-MFMA BConv column kernels support these parameters
+// at this NTT split.
+int mx_ok(const DevTables& tb, int log_r);
 
 // Two-pass transforms of x [items][nlimbs][N], limb r over prime first + r.
 hipError_t launch_ntt(const DevTables& tb, int log_r, uint64_t* x, int first, int nlimbs, int items, hipStream_t s);
@@ -19,8 +22,9 @@ hipError_t launch_intt(const DevTables& tb, int log_r, uint64_t* x, int first, i
 // Inverse block pass only (stages log_n-1 .. log_r) of src [items][nlimbs][N] over primes 0..nlimbs-1.
 hipError_t launch_intt_blocks(const DevTables& tb, int log_r, const uint64_t* src, uint64_t* dst, int nlimbs,
                               int items, hipStream_t s);
+// mfma: BConv on the int8 matrix cores (requires mx_ok) instead of FP64 / integer products.
 hipError_t launch_modup_cols(const DevTables& tb, int log_r, const uint64_t* t1, uint64_t* ext1, int j0, int nj,
-                             int nslots, int slot_stride, int tgt0, int tgt1, int items, hipStream_t s);
+                             int nslots, int slot_stride, int tgt0, int tgt1, int items, int mfma, hipStream_t s);
 // KeyMult over targets [tgt0, tgt1): one kernel for the Q limbs (skipped when
 // q_part is 0) and one for the P limbs.
 hipError_t launch_keymult_blocks(const DevTables& tb, int log_r, const uint64_t* d, const uint64_t* ext1,
@@ -32,7 +36,7 @@ hipError_t launch_moddown_km_blocks(const DevTables& tb, int log_r, const uint64
                                     const uint64_t* evk, const uint64_t* t2, uint64_t* out, int j0, int j1,
                                     int nslots, int slot_stride, int tgt0, int tgt1, int items, hipStream_t s);
 hipError_t launch_moddown_cols(const DevTables& tb, int log_r, const uint64_t* accp, uint64_t* t2, int tgt0,
-                               int tgt1, int items, hipStream_t s);
+                               int tgt1, int items, int mfma, hipStream_t s);
 hipError_t launch_moddown_blocks(const DevTables& tb, int log_r, const uint64_t* t2, const uint64_t* acc,
                                  uint64_t* out, int tgt0, int tgt1, int items, hipStream_t s);
 hipError_t launch_ext_blocks(const DevTables& tb, int log_r, uint64_t* ext, int items, hipStream_t s);

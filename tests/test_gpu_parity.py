@@ -118,6 +118,8 @@ def _plans(ks, P, log_n):
         for df, chunks in [(ks.DSOB, 1), (ks.DPOB, 1), (ks.DSOC, 2), (ks.DPOC, 3), (ks.STAGED, 1)]:
             chunks = min(chunks, P.ell)
             plans.append(ks.make_plan(df, chunks, log_r))
+            if log_r <= 4:  # the int8-MFMA BConv
+                plans.append(ks.make_plan(df, chunks, log_r, mfma=True))
     return plans
 
 
@@ -154,7 +156,9 @@ def full_case(ks, name):
 def test_keyswitch_benchmark_sizes(ks, name):
     G, P, s, s2, evk, d, ref, batch = full_case(ks, name)
     dd, ee = dev(d), dev(evk)
-    plans = [None, ks.make_plan(ks.DSOB), ks.make_plan(ks.DPOC, 4), ks.make_plan(ks.DSOC, 2)]
+    plans = [None, ks.make_plan(ks.DSOB), ks.make_plan(ks.DPOC, 4), ks.make_plan(ks.DSOC, 2),
+             ks.make_plan(ks.DPOB, 1, 4, mfma=True), ks.make_plan(ks.DSOC, 3, 3, mfma=True),
+             ks.make_plan(ks.STAGED, 1, 4, mfma=True)]
     for plan in plans:
         out = empty(ref.shape)
         ws = G.workspace(batch, plan)
@@ -229,6 +233,15 @@ def test_argument_errors(ks):
     assert e.value.code == ks.KS_EUNSUP
     with pytest.raises(ks.KsError) as e:
         G.keyswitch(d, evk, out, 1, ws, ks.make_plan(ks.DPOB, 1, 9))
+    assert e.value.code == ks.KS_EUNSUP
+    with pytest.raises(ks.KsError) as e:  # the MFMA BConv holds at most 16 rows per lane
+        G.keyswitch(d, evk, out, 1, ws, ks.make_plan(ks.DPOB, 1, 5, mfma=True))
+    assert e.value.code == ks.KS_EUNSUP
+    with pytest.raises(ks.KsError) as e:  # ... and at most 16 sources per BConv
+        ks.KsParams(1, 10, 20).workspace_bytes(1, ks.make_plan(ks.DPOB, 1, 2, mfma=True))
+    assert e.value.code == ks.KS_EUNSUP
+    with pytest.raises(ks.KsError) as e:
+        G.keyswitch(d, evk, out, 1, ws, ks.Plan(ks.DPOB, 1, 2, 6))
     assert e.value.code == ks.KS_EUNSUP
     with pytest.raises(ks.KsError) as e:
         G.ntt(d, P.nl - 1, 2, 1)
