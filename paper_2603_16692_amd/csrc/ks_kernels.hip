@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "ks_device.hpp"
 #include "ks_kernels.hpp"
@@ -61,6 +62,25 @@ __device__ __forceinline__ Tile xcd_tile(int ntiles, int items) {
   return Tile{tile, item, tile < ntiles};
 }
 inline unsigned xcd_grid(int ntiles, int items) { return (unsigned)(((ntiles + 7) / 8) * 8 * items); }
+
+// BlockNtt::fwd with the thread index hidden from the optimiser: a kernel that
+// runs several transforms would otherwise keep every LDS and twiddle address
+// of all rounds live from the first transform to the last, which costs more
+// registers than recomputing them.
+template <class B, class Ar>
+__device__ __forceinline__ void fwd_opaque(const Ar& A, typename Ar::T* v, typename Ar::T* ld, int tid,
+                                           uint32_t B0) {
+  int t = tid;
+  asm volatile("" : "+v"(t));
+  B::fwd(A, v, ld, t, B0);
+}
+template <class B, class Ar>
+__device__ __forceinline__ void inv_opaque(const Ar& A, typename Ar::T* v, typename Ar::T* ld, int tid,
+                                           uint32_t B0) {
+  int t = tid;
+  asm volatile("" : "+v"(t));
+  B::inv(A, v, ld, t, B0);
+}
 
 // ------------------------------------------------------- standalone passes
 
@@ -328,80 +348,71 @@ __device__ __forceinline__ uint64_t mx_fold_p(double lo, double hi, const LimbC&
   return ul + mul_shoup(uh, L.r32, L.r32_s, L.q) + L.cadj;
 }
 
-// Phase 2 of the MFMA column kernels for one target group: for each row r,
-// nm MFMA steps over the packed digits yp ([pairs][R][64] x 16 bytes) give
-// the partial sums of targets ta (lane half 0: 2h, ...) and tb2; fold, run
-// the forward column pass and store the rows of each target whose store flag
-// is set. Q groups store canonical residues, P groups [0, 4p).
-template <int LOGR, bool QG>
-__device__ __forceinline__ void mx_group(const DevTables& tb, const ulonglong2* yp, const ulonglong2* cst_g, int nm,
-                                         int ta, int tb2, bool sa, bool sb, uint64_t* oa, uint64_t* ob, size_t cc,
-                                         int M) {
+// Phase 2 of the MFMA column kernels for one target group. A lane in half h
+// holds the partial sums of targets 2h and 2h + 1 of the group; each is
+// finished in its own pass (PASS 0: accumulators 0..7, PASS 1: 8..15), which
+// runs the nm MFMA steps of every row r over the packed digits yp
+// ([pairs][R][64] x 16 bytes) again, so that only one target's R values are
+// live: for each row the fold mod t, then the forward column pass and, if
+// `st`, the store of the R rows. Q groups store canonical residues, P groups
+// values in [0, 4p).
+template <int LOGR, bool QG, int NM, int PASS>
+__device__ __forceinline__ void mx_target(const DevTables& tb, const ulonglong2* yp, const ulonglong2 (&cst)[NM],
+                                          int t0, int t1, bool st, uint64_t* o, size_t cc, int M) {
   constexpr int R = 1 << LOGR;
   const int lane = threadIdx.x & (TC - 1), h = lane >> 5;
   const int ycol = ((threadIdx.x / TC) & 1) * 32 + (lane & 31);
-  ulonglong2 cst[4];
-#pragma unroll
-  for (int m = 0; m < 4; ++m)
-    if (m < nm) cst[m] = cst_g[m * 64 + lane];
-  const LimbC& La = tb.limb[ta];
-  const LimbC& Lb = tb.limb[tb2];
+  const int t = h ? t1 : t0;
+  const LimbC& L = tb.limb[t];
   const size_t N = (size_t)M * R;
+  using T = typename std::conditional<QG, double, uint64_t>::type;
+  T z[R];
+  const double q = L.qd, qi = L.qinv, r32 = L.r32_d;
+  int yo = h * R * TC + ycol;  // digit words of row r of step m: yp[yo + 2 m R TC + r TC]
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    mx_v16i acc = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int m = 0; m < NM; ++m) acc = mx_step(cst[m], yp[yo + (2 * m * R + r) * TC], acc);
+    double lo, hi;
+    mx_halves<8 * PASS>(acc, lo, hi);
+    if constexpr (QG)
+      z[r] = mx_fold_q(lo, hi, q, qi, r32);
+    else
+      z[r] = mx_fold_p(lo, hi, L);
+    // One row at a time: this row's result is materialised here (the compiler
+    // would otherwise sink the folds below the loop and keep every row's
+    // accumulators live), and the next row's digit loads wait for it.
+    asm volatile("" : "+v"(z[r]), "+v"(yo));
+  }
   if constexpr (QG) {
-    const double qa = La.qd, qia = La.qinv, ra = La.r32_d;
-    const double qb = Lb.qd, qib = Lb.qinv, rb = Lb.r32_d;
-    double za[R], zb[R];
+    sub_fwd<LOGR>(ArF{q, qi, tb.twf_d + (size_t)t * N}, z, 1u);
+    if (st) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      mx_v16i acc = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-        if (m < nm) acc = mx_step(cst[m], yp[((2 * m + h) * R + r) * TC + ycol], acc);
-      double l0, h0, l1, h1;
-      mx_halves<0>(acc, l0, h0);
-      mx_halves<8>(acc, l1, h1);
-      za[r] = mx_fold_q(l0, h0, qa, qia, ra);
-      zb[r] = mx_fold_q(l1, h1, qb, qib, rb);
-      // Materialise this row's results here, so that the compiler does not
-      // sink the folds below the loop and keep all rows' accumulators live.
-      asm volatile("" : "+v"(za[r]), "+v"(zb[r]));
-    }
-    sub_fwd<LOGR>(ArF{qa, qia, tb.twf_d + (size_t)ta * N}, za, 1u);
-    if (sa) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) oa[cc + (size_t)r * M] = f_canon(za[r], qa, qia);
-    }
-    sub_fwd<LOGR>(ArF{qb, qib, tb.twf_d + (size_t)tb2 * N}, zb, 1u);
-    if (sb) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) ob[cc + (size_t)r * M] = f_canon(zb[r], qb, qib);
+      for (int r = 0; r < R; ++r) o[cc + (size_t)r * M] = f_canon(z[r], q, qi);
     }
   } else {
-    uint64_t za[R], zb[R];
+    sub_fwd<LOGR>(ArI{L.q, L.two_q, tb.twf + (size_t)t * N * 2}, z, 1u);
+    if (st) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      mx_v16i acc = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-        if (m < nm) acc = mx_step(cst[m], yp[((2 * m + h) * R + r) * TC + ycol], acc);
-      double l0, h0, l1, h1;
-      mx_halves<0>(acc, l0, h0);
-      mx_halves<8>(acc, l1, h1);
-      za[r] = mx_fold_p(l0, h0, La);
-      zb[r] = mx_fold_p(l1, h1, Lb);
-      asm volatile("" : "+v"(za[r]), "+v"(zb[r]));
-    }
-    sub_fwd<LOGR>(ArI{La.q, La.two_q, tb.twf + (size_t)ta * N * 2}, za, 1u);
-    if (sa) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) oa[cc + (size_t)r * M] = za[r];
-    }
-    sub_fwd<LOGR>(ArI{Lb.q, Lb.two_q, tb.twf + (size_t)tb2 * N * 2}, zb, 1u);
-    if (sb) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) ob[cc + (size_t)r * M] = zb[r];
+      for (int r = 0; r < R; ++r) o[cc + (size_t)r * M] = z[r];
     }
   }
+}
+
+// lt[4]: the group's four limbs (padding slots replaced by a stand-in limb,
+// wave-uniform); lane half h finishes targets lt[2h] (stored if sa, at oa)
+// and lt[2h + 1] (if sb, at ob).
+template <int LOGR, bool QG, int NM>
+__device__ __forceinline__ void mx_group(const DevTables& tb, const ulonglong2* yp, const ulonglong2* cst_g,
+                                         const int (&lt)[4], bool sa, bool sb, uint64_t* oa, uint64_t* ob,
+                                         size_t cc, int M) {
+  const int lane = threadIdx.x & (TC - 1);
+  ulonglong2 cst[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) cst[m] = cst_g[m * 64 + lane];
+  mx_target<LOGR, QG, NM, 0>(tb, yp, cst, lt[0], lt[2], sa, oa, cc, M);
+  mx_target<LOGR, QG, NM, 1>(tb, yp, cst, lt[1], lt[3], sb, ob, cc, M);
 }
 
 // ModUp columns with the int8-MFMA BConv: same arguments and output as
@@ -412,8 +423,8 @@ __device__ __forceinline__ void mx_group(const DevTables& tb, const ulonglong2* 
 // half w % 2 (lane l works on column (w % 2) * 32 + l % 32 of the workgroup)
 // and the target groups w/2, w/2 + 4, ...: per digit the Q targets outside
 // D_j in groups of four (in basis order), then the P targets.
-template <int LOGR>
-__global__ __launch_bounds__(CT) void k_modup_cols_mx(DevTables tb, const uint64_t* t1, uint64_t* ext1, int j0,
+template <int LOGR, int NM>
+__global__ __launch_bounds__(CT, LOGR == 4 ? 4 : 1) void k_modup_cols_mx(DevTables tb, const uint64_t* t1, uint64_t* ext1, int j0,
                                                      int nslots, int slot_stride, int tgt0, int tgt1, int log_m) {
   constexpr int R = 1 << LOGR;
   extern __shared__ ulonglong2 yp[];
@@ -427,7 +438,7 @@ __global__ __launch_bounds__(CT) void k_modup_cols_mx(DevTables tb, const uint64
   const int ell = tb.ell, nl = tb.nl, k = tb.k;
   const int lo = j * tb.alpha;
   const int na = min(lo + tb.alpha, ell) - lo;
-  const int nm = tb.up_nm;
+  constexpr int nm = NM;  // = tb.up_nm
   uint64_t* yw = reinterpret_cast<uint64_t*>(yp);
   for (int s = wv; s < 4 * nm; s += CW) {
     uint64_t y[R];
@@ -479,13 +490,15 @@ __global__ __launch_bounds__(CT) void k_modup_cols_mx(DevTables tb, const uint64
     const bool sa = clive && ta >= tgt0 && ta < tgt1;
     const bool sb = clive && tb2 >= tgt0 && tb2 < tgt1;
     const int pad = qg ? 0 : ell;  // stand-in limb for padding slots (never stored)
-    const int la = ta >= 0 ? ta : pad, lb = tb2 >= 0 ? tb2 : pad;
+    int lt[4];
+#pragma unroll
+    for (int tau = 0; tau < 4; ++tau) lt[tau] = tg[tau] >= 0 ? tg[tau] : pad;
+    uint64_t* oa = e + (size_t)lt[2 * h] * N;
+    uint64_t* ob = e + (size_t)lt[2 * h + 1] * N;
     if (qg)
-      mx_group<LOGR, true>(tb, yp, cst_j + (size_t)g * nm * 64, nm, la, lb, sa, sb, e + (size_t)la * N,
-                           e + (size_t)lb * N, cc, M);
+      mx_group<LOGR, true, NM>(tb, yp, cst_j + (size_t)g * nm * 64, lt, sa, sb, oa, ob, cc, M);
     else
-      mx_group<LOGR, false>(tb, yp, cst_j + (size_t)g * nm * 64, nm, la, lb, sa, sb, e + (size_t)la * N,
-                            e + (size_t)lb * N, cc, M);
+      mx_group<LOGR, false, NM>(tb, yp, cst_j + (size_t)g * nm * 64, lt, sa, sb, oa, ob, cc, M);
   }
 }
 
@@ -537,7 +550,7 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
         const uint64_t* src = ext1 + (((size_t)item * nslots + slot) * nl + t) * N + boff;
 #pragma unroll
         for (int i = 0; i < B::E; ++i) v[i] = u2d(src[B::fr_pos(tid, i)]);
-        B::fwd(A, v, ld, tid, B0);
+        fwd_opaque<B>(A, v, ld, tid, B0);
       }
       const uint64_t* k0 = evk + (((size_t)j * 2 + 0) * nl + t) * N + boff;
       const uint64_t* k1 = evk + (((size_t)j * 2 + 1) * nl + t) * N + boff;
@@ -577,7 +590,7 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
     const uint64_t* src = ext1 + (((size_t)item * nslots + slot) * nl + t) * N + boff;
 #pragma unroll
     for (int i = 0; i < B::E; ++i) v[i] = src[B::fr_pos(tid, i)];
-    B::fwd(A, v, lds, tid, B0);
+    fwd_opaque<B>(A, v, lds, tid, B0);
     const uint64_t* k0 = evk + (((size_t)j * 2 + 0) * nl + t) * N + boff;
     const uint64_t* k1 = evk + (((size_t)j * 2 + 1) * nl + t) * N + boff;
 #pragma unroll
@@ -606,10 +619,10 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
   }
   if (finalize) {
     const ArI Ai = ari(tb, L, t, true);
-    B::inv(Ai, s0, lds, tid, B0);
+    inv_opaque<B>(Ai, s0, lds, tid, B0);
 #pragma unroll
     for (int i = 0; i < B::E; ++i) a0[B::fr_pos(tid, i)] = s0[i];
-    B::inv(Ai, s1, lds, tid, B0);
+    inv_opaque<B>(Ai, s1, lds, tid, B0);
 #pragma unroll
     for (int i = 0; i < B::E; ++i) a1[B::fr_pos(tid, i)] = s1[i];
   } else {
@@ -696,8 +709,8 @@ __global__ __launch_bounds__(CT, LOGR <= 4 ? 4 : 2) void k_moddown_cols(DevTable
 // zero past the k sources and for columns past M). Phase 2: wave w takes the
 // column half w % 2 and the groups of four Q limbs w/2, w/2 + 4, ... that
 // meet [tgt0, tgt1); output t2 canonical.
-template <int LOGR>
-__global__ __launch_bounds__(CT) void k_moddown_cols_mx(DevTables tb, const uint64_t* accp, uint64_t* t2, int tgt0,
+template <int LOGR, int NM>
+__global__ __launch_bounds__(CT, LOGR == 4 ? 4 : 1) void k_moddown_cols_mx(DevTables tb, const uint64_t* accp, uint64_t* t2, int tgt0,
                                                        int tgt1, int log_m) {
   constexpr int R = 1 << LOGR;
   extern __shared__ ulonglong2 yp[];
@@ -708,7 +721,7 @@ __global__ __launch_bounds__(CT) void k_moddown_cols_mx(DevTables tb, const uint
   const bool live = c < (size_t)M;
   const int comp = blockIdx.y, item = blockIdx.z;
   const int ell = tb.ell, nl = tb.nl, k = tb.k;
-  const int nm = tb.dn_nm;
+  constexpr int nm = NM;  // = tb.dn_nm
   uint64_t* yw = reinterpret_cast<uint64_t*>(yp);
   for (int m = wv; m < 4 * nm; m += CW) {
     uint64_t y[R];
@@ -739,9 +752,11 @@ __global__ __launch_bounds__(CT) void k_moddown_cols_mx(DevTables tb, const uint
     const int ta = 4 * g + 2 * h, tb2 = ta + 1;
     const bool sa = clive && ta >= tgt0 && ta < tgt1;
     const bool sb = clive && tb2 >= tgt0 && tb2 < tgt1;
-    const int la = ta < ell ? ta : 0, lb = tb2 < ell ? tb2 : 0;
-    mx_group<LOGR, true>(tb, yp, cst + (size_t)g * nm * 64, nm, la, lb, sa, sb, o + (size_t)la * N,
-                         o + (size_t)lb * N, cc, M);
+    int lt[4];
+#pragma unroll
+    for (int tau = 0; tau < 4; ++tau) lt[tau] = 4 * g + tau < ell ? 4 * g + tau : 0;
+    mx_group<LOGR, true, NM>(tb, yp, cst + (size_t)g * nm * 64, lt, sa, sb, o + (size_t)lt[2 * h] * N,
+                             o + (size_t)lt[2 * h + 1] * N, cc, M);
   }
 }
 
@@ -782,12 +797,29 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_moddown_blocks(DevTabl
   }
 }
 
-// One block b of one Q limb i in [tgt0, tgt0 + ntgt) of one item per workgroup
-// (placed by xcd_tile), both components:
-// the digit-parallel plans defer the Q-limb KeyMult to here, so acc_Q never
-// goes through HBM. s_c = -NTT(t2_c) + sum_j ext_j * evk[j][c] (ext_j = d on
-// the digit's own limbs, else the forward block pass of ext1), then
-// out_c = s_c * P^-1 (canonical).
+// The twiddles one block pass reads, staged in LDS: entry x in [1, M) is
+// table entry ((R + b) << s) + x - 2^s with s = floor(log2 x), the twiddle of
+// local stage s and group x - 2^s of block b. BlockNtt with B0 = 1 and this
+// table computes what it computes with B0 = R + b and the global table.
+template <int LOGM, class T>
+__device__ __forceinline__ void stage_twiddles(T* tw, const T* table, uint32_t B0, int tid, int nthreads) {
+  for (int x = tid; x < (1 << LOGM); x += nthreads) {
+    if (x == 0) continue;
+    const int s = 31 - __clz(x);
+    tw[x] = table[(B0 << s) + (uint32_t)(x - (1 << s))];
+  }
+}
+
+// ModDown's last block pass with the Q-limb KeyMult of digit-parallel plans
+// folded in. One block b of one Q limb i in [tgt0, tgt0 + ntgt) of one item
+// per workgroup (placed by xcd_tile), all five forward block passes of the
+// limb share its twiddles, staged once in LDS:
+//   s_c = -NTT(t2_c) + sum_{j in [j0, j1)} ext_j * evk[j][c],
+//   ext_j = d (i in D_j) or the forward block pass of ext1 slot j,
+//   out_c = s_c * P^-1 (canonical).
+// t2 and ext1 canonical in, |values| <= 2q inside. The next input and the
+// key blocks of a digit are loaded before the transform that precedes their
+// use, so their latency overlaps it.
 template <int LOGM, int LOGE>
 __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4 : 1) void k_moddown_km_blocks(
     DevTables tb, const uint64_t* d, const uint64_t* ext1, const uint64_t* evk, const uint64_t* t2, uint64_t* out,
@@ -795,6 +827,9 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
   using B = BlockNtt<LOGM, LOGE>;
   extern __shared__ uint64_t lds[];
   double* ld = reinterpret_cast<double*>(lds);
+  // twiddles in LDS when the transform buffer leaves room for them
+  constexpr bool TWL = (B::LDS_WORDS + B::M) * sizeof(double) <= 160 * 1024;
+  double* tw = ld + B::LDS_WORDS;
   const size_t N = (size_t)1 << tb.log_n;
   const int R = (int)(N >> LOGM);
   const Tile tl = xcd_tile(R * ntgt, items);
@@ -803,29 +838,41 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
   const int i = tgt0 + tl.tile / R;
   const int item = tl.item;
   const LimbC L = tb.limb[i];
-  const uint32_t B0 = (uint32_t)R + b;
   const int nl = tb.nl, ell = tb.ell;
   const size_t boff = (size_t)b * B::M;
-  const ArF A = arf(tb, L, i, false);
-  double s0[B::E], s1[B::E], v[B::E];
+  const ArF A{L.qd, L.qinv, TWL ? tw : tb.twf_d + (size_t)i * N};
+  const uint32_t B0 = TWL ? 1u : (uint32_t)(R + b);
+  double s0[B::E], s1[B::E], v[B::E], nx[B::E];
   {
     const uint64_t* src = t2 + (((size_t)item * 2 + 0) * ell + i) * N + boff;
 #pragma unroll
     for (int e = 0; e < B::E; ++e) v[e] = u2d(src[B::fr_pos(tid, e)]);
-    B::fwd(A, v, ld, tid, B0);
-#pragma unroll
-    for (int e = 0; e < B::E; ++e) s0[e] = -v[e];
+  }
+  if constexpr (TWL) {
+    stage_twiddles<LOGM>(tw, tb.twf_d + (size_t)i * N, (uint32_t)(R + b), tid, B::T);
+    __syncthreads();
   }
   {
     const uint64_t* src = t2 + (((size_t)item * 2 + 1) * ell + i) * N + boff;
 #pragma unroll
-    for (int e = 0; e < B::E; ++e) v[e] = u2d(src[B::fr_pos(tid, e)]);
-    B::fwd(A, v, ld, tid, B0);
-#pragma unroll
-    for (int e = 0; e < B::E; ++e) s1[e] = -v[e];
+    for (int e = 0; e < B::E; ++e) nx[e] = u2d(src[B::fr_pos(tid, e)]);
   }
+  fwd_opaque<B>(A, v, ld, tid, B0);
+#pragma unroll
+  for (int e = 0; e < B::E; ++e) {
+    s0[e] = -v[e];
+    v[e] = nx[e];
+  }
+  fwd_opaque<B>(A, v, ld, tid, B0);
+#pragma unroll
+  for (int e = 0; e < B::E; ++e) s1[e] = -v[e];
   for (int j = j0; j < j1; ++j) {
     const int lo = j * tb.alpha;
+    const uint64_t* k0 = evk + (((size_t)j * 2 + 0) * nl + i) * N + boff;
+    const uint64_t* k1 = evk + (((size_t)j * 2 + 1) * nl + i) * N + boff;
+    double w0[B::E];  // the first key component is loaded ahead of the transform
+#pragma unroll
+    for (int e = 0; e < B::E; ++e) w0[e] = u2d(k0[B::cl_pos(tid, e)]);
     if (i >= lo && i < lo + tb.alpha) {
       const uint64_t* src = d + ((size_t)item * ell + i) * N + boff;
 #pragma unroll
@@ -835,17 +882,14 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
       const uint64_t* src = ext1 + (((size_t)item * nslots + slot) * nl + i) * N + boff;
 #pragma unroll
       for (int e = 0; e < B::E; ++e) v[e] = u2d(src[B::fr_pos(tid, e)]);
-      B::fwd(A, v, ld, tid, B0);
+      fwd_opaque<B>(A, v, ld, tid, B0);
     }
-    const uint64_t* k0 = evk + (((size_t)j * 2 + 0) * nl + i) * N + boff;
-    const uint64_t* k1 = evk + (((size_t)j * 2 + 1) * nl + i) * N + boff;
     // |v| <= 2q, key < q: each product is within 1.25q; the running sums start
     // within 1.375q + 1 and are folded every 4 digits, so they stay below 2^53
 #pragma unroll
     for (int e = 0; e < B::E; ++e) {
-      const int x = B::cl_pos(tid, e);
-      s0[e] += f_mul(v[e], u2d(k0[x]), L.qd, L.qinv);
-      s1[e] += f_mul(v[e], u2d(k1[x]), L.qd, L.qinv);
+      s0[e] += f_mul(v[e], w0[e], L.qd, L.qinv);
+      s1[e] += f_mul(v[e], u2d(k1[B::cl_pos(tid, e)]), L.qd, L.qinv);
     }
     if (((j - j0) & 3) == 3) {
 #pragma unroll
@@ -1109,15 +1153,25 @@ struct ModupCols {
     return hipGetLastError();
   }
 };
+template <int LOGR, int NM>
+hipError_t modup_cols_mx(const DevTables& tb, const uint64_t* t1, uint64_t* ext1, int j0, int nj, int nslots,
+                         int slot_stride, int tgt0, int tgt1, int items, int log_m, hipStream_t s) {
+  allow_lds<k_modup_cols_mx<LOGR, NM>>();
+  k_modup_cols_mx<LOGR, NM><<<col_grid(log_m, nj, items), dim3(CT), mx_lds_bytes(NM, LOGR), s>>>(
+      tb, t1, ext1, j0, nslots, slot_stride, tgt0, tgt1, log_m);
+  return hipGetLastError();
+}
 template <int LOGR>
 struct ModupColsMx {
-  static hipError_t run(const DevTables& tb, const uint64_t* t1, uint64_t* ext1, int j0, int nj, int nslots,
-                        int slot_stride, int tgt0, int tgt1, int items, int log_m, hipStream_t s) {
-    allow_lds<k_modup_cols_mx<LOGR>>();
-    const size_t lds = mx_lds_bytes(tb.up_nm, LOGR);
-    k_modup_cols_mx<LOGR><<<col_grid(log_m, nj, items), dim3(CT), lds, s>>>(tb, t1, ext1, j0, nslots, slot_stride,
-                                                                            tgt0, tgt1, log_m);
-    return hipGetLastError();
+  template <typename... A>
+  static hipError_t run(const DevTables& tb, A... a) {
+    switch (tb.up_nm) {
+      case 1: return modup_cols_mx<LOGR, 1>(tb, a...);
+      case 2: return modup_cols_mx<LOGR, 2>(tb, a...);
+      case 3: return modup_cols_mx<LOGR, 3>(tb, a...);
+      case 4: return modup_cols_mx<LOGR, 4>(tb, a...);
+      default: return hipErrorInvalidValue;
+    }
   }
 };
 template <int LOGM, int LOGE>
@@ -1157,14 +1211,25 @@ struct ModdownCols {
     return hipGetLastError();
   }
 };
+template <int LOGR, int NM>
+hipError_t moddown_cols_mx(const DevTables& tb, const uint64_t* accp, uint64_t* t2, int tgt0, int tgt1, int items,
+                           int log_m, hipStream_t s) {
+  allow_lds<k_moddown_cols_mx<LOGR, NM>>();
+  k_moddown_cols_mx<LOGR, NM><<<col_grid(log_m, 2, items), dim3(CT), mx_lds_bytes(NM, LOGR), s>>>(
+      tb, accp, t2, tgt0, tgt1, log_m);
+  return hipGetLastError();
+}
 template <int LOGR>
 struct ModdownColsMx {
-  static hipError_t run(const DevTables& tb, const uint64_t* accp, uint64_t* t2, int tgt0, int tgt1, int items,
-                        int log_m, hipStream_t s) {
-    allow_lds<k_moddown_cols_mx<LOGR>>();
-    const size_t lds = mx_lds_bytes(tb.dn_nm, LOGR);
-    k_moddown_cols_mx<LOGR><<<col_grid(log_m, 2, items), dim3(CT), lds, s>>>(tb, accp, t2, tgt0, tgt1, log_m);
-    return hipGetLastError();
+  template <typename... A>
+  static hipError_t run(const DevTables& tb, A... a) {
+    switch (tb.dn_nm) {
+      case 1: return moddown_cols_mx<LOGR, 1>(tb, a...);
+      case 2: return moddown_cols_mx<LOGR, 2>(tb, a...);
+      case 3: return moddown_cols_mx<LOGR, 3>(tb, a...);
+      case 4: return moddown_cols_mx<LOGR, 4>(tb, a...);
+      default: return hipErrorInvalidValue;
+    }
   }
 };
 template <int LOGM, int LOGE>
@@ -1179,6 +1244,12 @@ struct ModdownBlocks {
   }
 };
 template <int LOGM, int LOGE>
+size_t km_lds() {
+  using B = BlockNtt<LOGM, LOGE>;
+  const size_t with_tw = sizeof(double) * (B::LDS_WORDS + B::M);
+  return with_tw <= 160 * 1024 ? with_tw : block_lds<LOGM, LOGE>();
+}
+template <int LOGM, int LOGE>
 struct ModdownKmBlocks {
   static hipError_t run(const DevTables& tb, const uint64_t* d, const uint64_t* ext1, const uint64_t* evk,
                         const uint64_t* t2, uint64_t* out, int j0, int j1, int nslots, int slot_stride, int tgt0,
@@ -1186,7 +1257,7 @@ struct ModdownKmBlocks {
     using B = BlockNtt<LOGM, LOGE>;
     allow_lds<k_moddown_km_blocks<LOGM, LOGE>>();
     k_moddown_km_blocks<LOGM, LOGE><<<dim3(xcd_grid((tgt1 - tgt0) << (tb.log_n - LOGM), items)), dim3(B::T),
-                                      block_lds<LOGM, LOGE>(), s>>>(tb, d, ext1, evk, t2, out, j0, j1, nslots,
+                                      km_lds<LOGM, LOGE>(), s>>>(tb, d, ext1, evk, t2, out, j0, j1, nslots,
                                                                     slot_stride, tgt0, tgt1 - tgt0, items);
     return hipGetLastError();
   }
