@@ -30,6 +30,35 @@ WORKLOADS = {
 }
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes of one launch of the dominant kernel, from two rocprofv3 --pmc
+# runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
+# scaled by what the same counter reads for a plain 1 GiB device copy
+# (--copy-calibration): FETCH_SIZE reads half the copied bytes, WRITE_SIZE all
+# of them. The figure holds only for the kernel sources it was measured on
+# (sha256 below) and for the same workload and plan; otherwise "traffic" is null.
+# The rocprofv3 summaries it comes from are under profiles/.
+TRAFFIC = None
+TRAFFIC_SOURCES = ["paper_2603_16692_amd/csrc/ks_kernels.hip", "paper_2603_16692_amd/csrc/ks_device.hpp"]
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, plan_repr, kernel):
+    """HBM bytes per launch of `kernel` from the stored counters, or None."""
+    t = TRAFFIC
+    if not t or t["workload"] != workload or t["plan"] != plan_repr or t["kernel"] != kernel:
+        return None
+    if t["sources_sha256"] != kernel_sources_sha256():
+        return None
+    return int((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024)
+
 
 def kernel_bytes(G, plan, batch, kind):
     """Algorithmic HBM bytes of all launches of `kind` in one step: each input
@@ -79,8 +108,11 @@ def main():
     ap.add_argument("--plan", default="", help="dataflow[,chunks[,log_r[,mfma]]] e.g. DPOB or DSOC,2,3 or DPOB,1,4,mfma")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the library's default plan instead of tuning")
+    ap.add_argument("--tune", action="store_true", help="tune even if a shipped tuned plan exists")
+    ap.add_argument("--save-tuned", default="", help="merge the tuning winner into this JSON table")
     ap.add_argument("--tune-plans", type=int, default=0, help="candidate plans the tuner times (0 = all)")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay measurement")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain single-ciphertext measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
@@ -135,16 +167,25 @@ def main():
     stream = torch.cuda.current_stream()
 
     tuning = None
+    if plan is None and not args.tune and not args.no_tune:
+        # the plan an earlier tuning run on this hardware chose, if shipped
+        from paper_2603_16692_amd import autotune
+        plan = autotune.cached_plan(G, batch, autotune.shipped_cache())
+        if plan is not None:
+            tuning = {"source": "shipped tuning table", "plan": repr(plan)}
     if plan is None and args.no_tune:
         plan = G.default_plan(batch)
     elif plan is None:
         # per-parameter dataflow choice by measurement (untimed setup)
         from paper_2603_16692_amd import autotune
         cands = autotune.prior_order(G, batch, autotune.candidate_plans(G, batch))
+        table = autotune.load_cache(args.save_tuned) if args.save_tuned else {}
         plan, results = autotune.tune(G, d, evk, batch, plans=cands[:args.tune_plans] if args.tune_plans else cands,
-                                      reps=3, trials=2)
+                                      reps=3, trials=2, cache=table)
+        if args.save_tuned:
+            autotune.save_cache(table, args.save_tuned)
         ranked = sorted(results, key=lambda r: r["ms"])
-        tuning = {"plans_tried": len(results), "best": ranked[0]["name"],
+        tuning = {"source": "tuned in this run", "plans_tried": len(results), "best": ranked[0]["name"],
                   "best_ms": round(ranked[0]["ms"], 4), "worst": ranked[-1]["name"],
                   "worst_ms": round(ranked[-1]["ms"], 4),
                   "default_ms": round(next((r["ms"] for r in results
@@ -189,7 +230,7 @@ def main():
 
     # plain single-ciphertext path on the same parameters (default plan)
     plain = None
-    if batch > 1:
+    if batch > 1 and not args.no_plain:
         d1 = d[:1].contiguous()
         out1 = out[:1].contiguous()
         ws1 = G.workspace(1)
@@ -231,7 +272,8 @@ def main():
         per_launch = nbytes / per_step
         achieved = per_launch / (dom_avg_ms / 1e3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(args.workload, repr(plan), ks.KIND_NAMES[dominant]),
                     "kernel": ks.KIND_NAMES[dominant], "kernel_avg_ms": round(dom_avg_ms, 4),
                     "launches_per_step": per_step, "algorithmic_bytes_per_launch": int(per_launch)}
 

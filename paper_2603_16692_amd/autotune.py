@@ -86,6 +86,15 @@ def _cache_key(params, batch: int) -> str:
     return f"{arch}|rocm{rocm}|dnum{params.dnum}|logn{params.log_n}|L{params.ell}|B{batch}"
 
 
+SHIPPED_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_plans.json")
+
+
+def shipped_cache() -> dict:
+    """Winners of earlier tuning runs on this hardware, shipped with the
+    package (same keys and entries as the tuning cache)."""
+    return load_cache(SHIPPED_PATH)
+
+
 def default_cache_path() -> str:
     return os.environ.get("KS_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "ks_autotune.json"))
 

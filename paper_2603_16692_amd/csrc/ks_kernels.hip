@@ -817,9 +817,9 @@ __device__ __forceinline__ void stage_twiddles(T* tw, const T* table, uint32_t B
 //   s_c = -NTT(t2_c) + sum_{j in [j0, j1)} ext_j * evk[j][c],
 //   ext_j = d (i in D_j) or the forward block pass of ext1 slot j,
 //   out_c = s_c * P^-1 (canonical).
-// t2 and ext1 canonical in, |values| <= 2q inside. The next input and the
-// key blocks of a digit are loaded before the transform that precedes their
-// use, so their latency overlaps it.
+// t2 and ext1 canonical in, |values| <= 2q inside. Inputs and key blocks are
+// loaded before the transform that precedes their use, so that their latency
+// overlaps it.
 template <int LOGM, int LOGE>
 __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4 : 1) void k_moddown_km_blocks(
     DevTables tb, const uint64_t* d, const uint64_t* ext1, const uint64_t* evk, const uint64_t* t2, uint64_t* out,
@@ -827,7 +827,6 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
   using B = BlockNtt<LOGM, LOGE>;
   extern __shared__ uint64_t lds[];
   double* ld = reinterpret_cast<double*>(lds);
-  // twiddles in LDS when the transform buffer leaves room for them
   constexpr bool TWL = (B::LDS_WORDS + B::M) * sizeof(double) <= 160 * 1024;
   double* tw = ld + B::LDS_WORDS;
   const size_t N = (size_t)1 << tb.log_n;
@@ -842,11 +841,28 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
   const size_t boff = (size_t)b * B::M;
   const ArF A{L.qd, L.qinv, TWL ? tw : tb.twf_d + (size_t)i * N};
   const uint32_t B0 = TWL ? 1u : (uint32_t)(R + b);
-  double s0[B::E], s1[B::E], v[B::E], nx[B::E];
+  const int own = i / tb.alpha;  // the digit whose limbs include i: its input is d, already in NTT form
+  // Loads ahead of use: always the second t2 component and the first key
+  // component of a digit; with DEEP also the next digit's input and the
+  // second key component (registers allow it up to blocks of 2^12).
+  constexpr bool DEEP = LOGM <= 12;
+  // input of digit j: d (CL layout) for the own digit, else ext1 (FR layout)
+  auto load_digit = [&](int j, double* x) {
+    if (j == own) {
+      const uint64_t* src = d + ((size_t)item * ell + i) * N + boff;
+#pragma unroll
+      for (int e = 0; e < B::E; ++e) x[e] = u2d(src[B::cl_pos(tid, e)]);
+    } else {
+      const uint64_t* src = ext1 + (((size_t)item * nslots + (slot_stride ? j : 0)) * nl + i) * N + boff;
+#pragma unroll
+      for (int e = 0; e < B::E; ++e) x[e] = u2d(src[B::fr_pos(tid, e)]);
+    }
+  };
+  double s0[B::E], s1[B::E], cur[B::E], nxt[B::E];
   {
     const uint64_t* src = t2 + (((size_t)item * 2 + 0) * ell + i) * N + boff;
 #pragma unroll
-    for (int e = 0; e < B::E; ++e) v[e] = u2d(src[B::fr_pos(tid, e)]);
+    for (int e = 0; e < B::E; ++e) cur[e] = u2d(src[B::fr_pos(tid, e)]);
   }
   if constexpr (TWL) {
     stage_twiddles<LOGM>(tw, tb.twf_d + (size_t)i * N, (uint32_t)(R + b), tid, B::T);
@@ -855,41 +871,45 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
   {
     const uint64_t* src = t2 + (((size_t)item * 2 + 1) * ell + i) * N + boff;
 #pragma unroll
-    for (int e = 0; e < B::E; ++e) nx[e] = u2d(src[B::fr_pos(tid, e)]);
+    for (int e = 0; e < B::E; ++e) nxt[e] = u2d(src[B::fr_pos(tid, e)]);
   }
-  fwd_opaque<B>(A, v, ld, tid, B0);
+  fwd_opaque<B>(A, cur, ld, tid, B0);
 #pragma unroll
   for (int e = 0; e < B::E; ++e) {
-    s0[e] = -v[e];
-    v[e] = nx[e];
+    s0[e] = -cur[e];
+    cur[e] = nxt[e];
   }
-  fwd_opaque<B>(A, v, ld, tid, B0);
+  if (DEEP && j0 < j1) load_digit(j0, nxt);
+  fwd_opaque<B>(A, cur, ld, tid, B0);
 #pragma unroll
-  for (int e = 0; e < B::E; ++e) s1[e] = -v[e];
+  for (int e = 0; e < B::E; ++e) s1[e] = -cur[e];
   for (int j = j0; j < j1; ++j) {
-    const int lo = j * tb.alpha;
+    if constexpr (DEEP) {
+#pragma unroll
+      for (int e = 0; e < B::E; ++e) cur[e] = nxt[e];
+    }
     const uint64_t* k0 = evk + (((size_t)j * 2 + 0) * nl + i) * N + boff;
     const uint64_t* k1 = evk + (((size_t)j * 2 + 1) * nl + i) * N + boff;
-    double w0[B::E];  // the first key component is loaded ahead of the transform
-#pragma unroll
-    for (int e = 0; e < B::E; ++e) w0[e] = u2d(k0[B::cl_pos(tid, e)]);
-    if (i >= lo && i < lo + tb.alpha) {
-      const uint64_t* src = d + ((size_t)item * ell + i) * N + boff;
-#pragma unroll
-      for (int e = 0; e < B::E; ++e) v[e] = u2d(src[B::cl_pos(tid, e)]);
-    } else {
-      const int slot = slot_stride ? j : 0;
-      const uint64_t* src = ext1 + (((size_t)item * nslots + slot) * nl + i) * N + boff;
-#pragma unroll
-      for (int e = 0; e < B::E; ++e) v[e] = u2d(src[B::fr_pos(tid, e)]);
-      fwd_opaque<B>(A, v, ld, tid, B0);
-    }
-    // |v| <= 2q, key < q: each product is within 1.25q; the running sums start
-    // within 1.375q + 1 and are folded every 4 digits, so they stay below 2^53
+    double w0[B::E], w1[B::E];
 #pragma unroll
     for (int e = 0; e < B::E; ++e) {
-      s0[e] += f_mul(v[e], w0[e], L.qd, L.qinv);
-      s1[e] += f_mul(v[e], u2d(k1[B::cl_pos(tid, e)]), L.qd, L.qinv);
+      w0[e] = u2d(k0[B::cl_pos(tid, e)]);
+      if constexpr (DEEP) w1[e] = u2d(k1[B::cl_pos(tid, e)]);
+    }
+    if constexpr (DEEP) {
+      if (j + 1 < j1) load_digit(j + 1, nxt);
+    } else {
+      load_digit(j, cur);
+    }
+    if (j != own) fwd_opaque<B>(A, cur, ld, tid, B0);
+    if constexpr (!DEEP) {
+#pragma unroll
+      for (int e = 0; e < B::E; ++e) w1[e] = u2d(k1[B::cl_pos(tid, e)]);
+    }
+#pragma unroll
+    for (int e = 0; e < B::E; ++e) {
+      s0[e] += f_mul(cur[e], w0[e], L.qd, L.qinv);
+      s1[e] += f_mul(cur[e], w1[e], L.qd, L.qinv);
     }
     if (((j - j0) & 3) == 3) {
 #pragma unroll
