@@ -37,7 +37,9 @@ HBM_PEAK_GBS = 8000.0
 # of them. The figure holds only for the kernel sources it was measured on
 # (sha256 below) and for the same workload and plan; otherwise "traffic" is null.
 # The rocprofv3 summaries it comes from are under profiles/.
-TRAFFIC = None
+TRAFFIC = {"workload": "c2", "plan": "Plan(DPOB, chunks=1, log_r=4, mfma)", "kernel": "moddown_blocks",
+           "fetch_kib": 509072.4, "fetch_scale": 2.0, "write_kib": 344064.0, "write_scale": 1.0,
+           "sources_sha256": "4f7c654442771b3337e247b108b3596ca26b2e027b42100c3bcdb137eb594d3c"}
 TRAFFIC_SOURCES = ["paper_2603_16692_amd/csrc/ks_kernels.hip", "paper_2603_16692_amd/csrc/ks_device.hpp"]
 
 
@@ -105,7 +107,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--batch", type=int, default=0, help="override the workload's batch size")
-    ap.add_argument("--plan", default="", help="dataflow[,chunks[,log_r[,mfma]]] e.g. DPOB or DSOC,2,3 or DPOB,1,4,mfma")
+    ap.add_argument("--plan", default="",
+                    help="dataflow[,chunks[,log_r[,options]]], options mfma and/or split joined by '+', "
+                         "e.g. DPOB or DSOC,2,3 or DPOB,1,4,mfma+split")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the library's default plan instead of tuning")
     ap.add_argument("--tune", action="store_true", help="tune even if a shipped tuned plan exists")
@@ -158,7 +162,8 @@ def main():
         df = {"DSOB": ks.DSOB, "DPOB": ks.DPOB, "DSOC": ks.DSOC, "DPOC": ks.DPOC, "STAGED": ks.STAGED}[parts[0]]
         chunks = int(parts[1]) if len(parts) > 1 else 1
         log_r = int(parts[2]) if len(parts) > 2 else -1
-        plan = ks.make_plan(df, chunks, log_r, len(parts) > 3 and parts[3] == "mfma")
+        opts = parts[3].split("+") if len(parts) > 3 else []
+        plan = ks.make_plan(df, chunks, log_r, "mfma" in opts, "split" in opts)
 
     to_dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda")
     d = to_dev(ciphertext_batch(G.moduli[:ell], G.n, batch))

@@ -73,7 +73,7 @@ typedef struct {
   int chunks;   /* output partitions for KS_DSOC / KS_DPOC (1..64), else ignored */
   int log_r;    /* NTT split N = 2^log_r * M: 2^log_r rows per column, blocks of M
                    coefficients (0 = one block pass, up to 5); negative = default */
-  int flags;    /* 0 or KS_PLAN_MFMA_BCONV; other bits are rejected (KS_EUNSUP) */
+  int flags;    /* KS_PLAN_MFMA_BCONV | KS_PLAN_SPLIT_STREAMS; other bits are rejected (KS_EUNSUP) */
 } ks_plan;
 
 /* Plan flag: run ModUp's and ModDown's fast base conversion (the BConv of
@@ -85,6 +85,18 @@ typedef struct {
    have at most 16 primes and log_r <= 4 (ks_keyswitch returns KS_EUNSUP
    otherwise). */
 #define KS_PLAN_MFMA_BCONV 1
+
+/* Plan flag: with batch >= 2, run items [batch/2, batch) on a second stream
+   owned by the parameter handle while items [0, batch/2) run on the caller's
+   stream, so that the kernels of the two halves share the GPU (one half's
+   memory stalls are filled with the other half's arithmetic). The call still
+   orders as one unit on the caller's stream: the second stream first waits
+   for the work already enqueued there, and the caller's stream waits for the
+   second half at the end (also under HIP-graph capture). The workspace is
+   the sum of those of the two halves (ks_workspace_bytes). Concurrent calls
+   with one handle from several host threads are serialised around this
+   fork and join. */
+#define KS_PLAN_SPLIT_STREAMS 2
 
 typedef struct {
   int n, log_n, ell, k, alpha, dnum, ndig;

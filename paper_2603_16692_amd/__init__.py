@@ -28,6 +28,7 @@ KS_SET_P = -1
 DSOB, DPOB, DSOC, DPOC, STAGED = 0, 1, 2, 3, 4
 DATAFLOW_NAMES = {DSOB: "DSOB", DPOB: "DPOB", DSOC: "DSOC", DPOC: "DPOC", STAGED: "STAGED"}
 PLAN_MFMA_BCONV = 1  # ks_plan.flags: BConv as an exact int8 product on the matrix cores
+PLAN_SPLIT_STREAMS = 2  # ks_plan.flags: the two halves of a batch on two streams
 
 
 class Plan(ctypes.Structure):
@@ -36,8 +37,9 @@ class Plan(ctypes.Structure):
 
     def __repr__(self):
         mx = ", mfma" if self.flags & PLAN_MFMA_BCONV else ""
+        sp = ", split" if self.flags & PLAN_SPLIT_STREAMS else ""
         return (f"Plan({DATAFLOW_NAMES.get(self.dataflow, self.dataflow)}, chunks={self.chunks}, "
-                f"log_r={self.log_r}{mx})")
+                f"log_r={self.log_r}{mx}{sp})")
 
     def key(self):
         return (self.dataflow, self.chunks, self.log_r, self.flags)
@@ -114,10 +116,11 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def make_plan(dataflow=DPOB, chunks=1, log_r=-1, mfma=False):
+def make_plan(dataflow=DPOB, chunks=1, log_r=-1, mfma=False, split=False):
     """A plan; log_r < 0 selects the library's default NTT split; mfma selects
-    the int8 matrix-core BConv."""
-    return Plan(dataflow, chunks, log_r, PLAN_MFMA_BCONV if mfma else 0)
+    the int8 matrix-core BConv; split runs the two halves of a batch on two
+    streams."""
+    return Plan(dataflow, chunks, log_r, (PLAN_MFMA_BCONV if mfma else 0) | (PLAN_SPLIT_STREAMS if split else 0))
 
 
 class KsParams:

@@ -22,7 +22,8 @@ import statistics
 
 import torch
 
-from . import DPOB, DPOC, DSOB, DSOC, STAGED, DATAFLOW_NAMES, HipEvents, KsError, make_plan
+from . import (DPOB, DPOC, DSOB, DSOC, STAGED, DATAFLOW_NAMES, PLAN_MFMA_BCONV, PLAN_SPLIT_STREAMS, HipEvents,
+               KsError, make_plan)
 
 WORD = 8
 MALL_BYTES = 256 << 20
@@ -42,21 +43,25 @@ def footprint_bytes(dnum: int, n: int, ell: int, dataflow: int, chunks: int = 1,
     return f
 
 
-def candidate_plans(params, batch: int, chunk_range=CHUNK_RANGE, mfma=(False, True)):
+def candidate_plans(params, batch: int, chunk_range=CHUNK_RANGE, mfma=(False, True), split=None):
     """Every plan libks accepts for these parameters and batch, with the
-    FP64 / integer BConv and with the int8-MFMA BConv."""
+    FP64 / integer BConv and with the int8-MFMA BConv, and (batch >= 2) with
+    the batch on one stream or split over two."""
+    if split is None:
+        split = (False, True) if batch >= 2 else (False,)
     plans = []
-    for mx in mfma:
-        for log_r in range(0, 6):
-            log_m = params.log_n - log_r
-            if log_m < 3 or log_m > 14:
-                continue
-            for df in (DSOB, DPOB, STAGED):
-                plans.append(make_plan(df, 1, log_r, mx))
-            for df in (DSOC, DPOC):
-                for c in chunk_range:
-                    if c <= params.ell:
-                        plans.append(make_plan(df, c, log_r, mx))
+    for sp in split:
+        for mx in mfma:
+            for log_r in range(0, 6):
+                log_m = params.log_n - log_r
+                if log_m < 3 or log_m > 14:
+                    continue
+                for df in (DSOB, DPOB, STAGED):
+                    plans.append(make_plan(df, 1, log_r, mx, sp))
+                for df in (DSOC, DPOC):
+                    for c in chunk_range:
+                        if c <= params.ell:
+                            plans.append(make_plan(df, c, log_r, mx, sp))
     valid = []
     for p in plans:
         try:
@@ -176,12 +181,28 @@ def cached_plan(params, batch: int, cache: dict):
     if not e:
         return None
     df, chunks, log_r = e["plan"][:3]
-    p = make_plan(df, chunks, log_r, bool(e["plan"][3]) if len(e["plan"]) > 3 else False)
+    flags = e["plan"][3] if len(e["plan"]) > 3 else 0
+    p = make_plan(df, chunks, log_r, bool(flags & PLAN_MFMA_BCONV), bool(flags & PLAN_SPLIT_STREAMS))
     try:
         params.workspace_bytes(batch, p)
     except KsError:
         return None
     return p
+
+
+def plan_for(params, batch: int, cache: dict):
+    """The cached winner for this batch, else the winner cached for the same
+    device and parameter set at the nearest other batch size, else None."""
+    p = cached_plan(params, batch, cache)
+    if p is not None:
+        return p
+    head = _cache_key(params, batch).rsplit("|B", 1)[0] + "|B"
+    near = sorted((abs(int(k[len(head):]) - batch), k) for k in cache if k.startswith(head))
+    for _, k in near:
+        p = cached_plan(params, int(k[len(head):]), cache)
+        if p is not None:
+            return p
+    return None
 
 
 def describe(plan) -> str:

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -19,6 +20,11 @@ struct ks_params {
   ks::DevTables tb;
   void* blob = nullptr;
   int device = 0;
+  // Second stream of KS_PLAN_SPLIT_STREAMS plans, with the fork and join
+  // events; `split` serialises their use by concurrent callers.
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  std::mutex split;
 };
 
 namespace {
@@ -82,7 +88,7 @@ int resolve_plan(const ks_params* p, const ks_plan* in, ks_plan& out) {
   } else {
     out = ks_plan{KS_DPOB, 1, -1, 0};
   }
-  if (out.flags & ~KS_PLAN_MFMA_BCONV) return KS_EUNSUP;
+  if (out.flags & ~(KS_PLAN_MFMA_BCONV | KS_PLAN_SPLIT_STREAMS)) return KS_EUNSUP;
   if (out.dataflow < KS_DSOB || out.dataflow > KS_STAGED) return KS_EUNSUP;
   if (out.log_r < 0) out.log_r = default_log_r(p->hp.log_n);
   const int log_m = p->hp.log_n - out.log_r;
@@ -128,6 +134,19 @@ Layout layout(const ks_params* p, int batch, const ks_plan& plan) {
   L.t2 = L.acc + up256(B * 2 * nl * N * W);
   L.total = L.t2 + up256(B * 2 * ell * N * W);
   return L;
+}
+
+// A split plan runs items [0, b0) on the caller's stream and [b0, batch) on
+// the handle's second stream, each with its own workspace.
+bool split_batch(const ks_plan& plan, int batch, int& b0) {
+  b0 = batch / 2;
+  return (plan.flags & KS_PLAN_SPLIT_STREAMS) && batch >= 2;
+}
+
+size_t workspace_total(const ks_params* p, int batch, const ks_plan& plan) {
+  int b0;
+  if (split_batch(plan, batch, b0)) return layout(p, b0, plan).total + layout(p, batch - b0, plan).total;
+  return layout(p, batch, plan).total;
 }
 
 void chunk_range(int n, int c, int i, int& a, int& b) {
@@ -289,12 +308,22 @@ int ks_params_create(int dnum, int log_n, int ell, ks_params** out) {
   rebase(p->tb.up_mat_d);
   rebase(p->tb.dn_mat_d);
   rebase(p->tb.dn_pinv_d);
+  e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    ks_params_destroy(p);
+    return hip_fail(e);
+  }
   *out = p;
   return KS_OK;
 }
 
 void ks_params_destroy(ks_params* p) {
   if (!p) return;
+  if (p->side) (void)hipStreamDestroy(p->side);
+  if (p->fork) (void)hipEventDestroy(p->fork);
+  if (p->join) (void)hipEventDestroy(p->join);
   if (p->blob) (void)hipFree(p->blob);
   delete p;
 }
@@ -328,7 +357,7 @@ int ks_workspace_bytes(const ks_params* p, int batch, const ks_plan* plan, size_
   ks_plan pl;
   const int rc = resolve_plan(p, plan, pl);
   if (rc != KS_OK) return rc;
-  *bytes = layout(p, batch, pl).total;
+  *bytes = workspace_total(p, batch, pl);
   return KS_OK;
 }
 
@@ -338,10 +367,12 @@ int ks_launch_count(const ks_params* p, int batch, const ks_plan* plan) {
   const int rc = resolve_plan(p, plan, pl);
   if (rc != KS_OK) return rc;
   if (batch == 0) return 0;
-  if (pl.dataflow == KS_STAGED) return 4 + 1 + 3;
+  int b0;
+  const int parts = split_batch(pl, batch, b0) ? 2 : 1;
+  if (pl.dataflow == KS_STAGED) return parts * (4 + 1 + 3);
   int n = 0;
   run_fused(p, pl, nullptr, nullptr, nullptr, batch, nullptr, nullptr, &n);
-  return n;
+  return parts * n;
 }
 
 static int check_limbs(const ks_params* p, int first, int n_limbs, int batch) {
@@ -419,6 +450,22 @@ int ks_moddown(const ks_params* p, const uint64_t* acc, uint64_t* out, int batch
   return run_moddown(p, pl, acc, out, batch, accp, t2, (hipStream_t)stream);
 }
 
+// One KeySwitch of `batch` items on stream s with workspace ws (no split).
+static int keyswitch_on(const ks_params* p, const ks_plan& pl, const uint64_t* d, const uint64_t* evk, uint64_t* out,
+                        int batch, char* ws, hipStream_t s) {
+  if (pl.dataflow == KS_STAGED) {
+    const Layout L = layout(p, batch, pl);
+    uint64_t* ext = reinterpret_cast<uint64_t*>(ws + L.ext);
+    uint64_t* acc = reinterpret_cast<uint64_t*>(ws + L.acc);
+    int rc;
+    if ((rc = run_modup(p, pl, d, ext, batch, reinterpret_cast<uint64_t*>(ws + L.t1), s)) != KS_OK) return rc;
+    KS_TRY(traced(KS_K_KEYMULT, s, [&] { return ks::launch_keymult(p->tb, ext, evk, acc, batch, s); }));
+    return run_moddown(p, pl, acc, out, batch, reinterpret_cast<uint64_t*>(ws + L.accp),
+                       reinterpret_cast<uint64_t*>(ws + L.t2), s);
+  }
+  return run_fused(p, pl, d, evk, out, batch, ws, s, nullptr);
+}
+
 int ks_keyswitch(const ks_params* p, const uint64_t* d, const uint64_t* evk, uint64_t* out, int batch,
                  const ks_plan* plan, void* ws, void* stream) {
   if (!p) return KS_ENULL;
@@ -431,17 +478,23 @@ int ks_keyswitch(const ks_params* p, const uint64_t* d, const uint64_t* evk, uin
       (rc = check_ptr(ws)) != KS_OK)
     return rc;
   hipStream_t s = (hipStream_t)stream;
-  if (pl.dataflow == KS_STAGED) {
-    const Layout L = layout(p, batch, pl);
-    char* w = reinterpret_cast<char*>(ws);
-    uint64_t* ext = reinterpret_cast<uint64_t*>(w + L.ext);
-    uint64_t* acc = reinterpret_cast<uint64_t*>(w + L.acc);
-    if ((rc = run_modup(p, pl, d, ext, batch, reinterpret_cast<uint64_t*>(w + L.t1), s)) != KS_OK) return rc;
-    KS_TRY(traced(KS_K_KEYMULT, s, [&] { return ks::launch_keymult(p->tb, ext, evk, acc, batch, s); }));
-    return run_moddown(p, pl, acc, out, batch, reinterpret_cast<uint64_t*>(w + L.accp),
-                       reinterpret_cast<uint64_t*>(w + L.t2), s);
-  }
-  return run_fused(p, pl, d, evk, out, batch, reinterpret_cast<char*>(ws), s, nullptr);
+  char* w = reinterpret_cast<char*>(ws);
+  int b0;
+  if (!split_batch(pl, batch, b0)) return keyswitch_on(p, pl, d, evk, out, batch, w, s);
+  // Items [b0, batch) on the second stream, after everything already on s;
+  // s then waits for them, so the call still completes in stream order on s.
+  const size_t N = p->hp.n, ell = p->hp.ell;
+  const size_t ws0 = layout(p, b0, pl).total;
+  std::lock_guard<std::mutex> lock(const_cast<ks_params*>(p)->split);
+  KS_TRY(hipEventRecord(p->fork, s));
+  KS_TRY(hipStreamWaitEvent(p->side, p->fork, 0));
+  if ((rc = keyswitch_on(p, pl, d + (size_t)b0 * ell * N, evk, out + (size_t)b0 * 2 * ell * N, batch - b0, w + ws0,
+                         p->side)) != KS_OK)
+    return rc;
+  KS_TRY(hipEventRecord(p->join, p->side));
+  if ((rc = keyswitch_on(p, pl, d, evk, out, b0, w, s)) != KS_OK) return rc;
+  KS_TRY(hipStreamWaitEvent(s, p->join, 0));
+  return KS_OK;
 }
 
 const char* ks_strerror(int code) {

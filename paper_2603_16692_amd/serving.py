@@ -264,6 +264,14 @@ def serve_benchmark(n_requests: int = 4000, loads=(0.5, 0.8), slots: int = 2, bu
     torch.cuda.synchronize()
     max_batch = {k: v[3] for k, v in SERVE_SETS.items()}
     shares = {k: v[4] for k, v in SERVE_SETS.items()}
+    # per-set plans from the shipped tuning table (the library default where none fits)
+    from . import autotune
+    table = autotune.shipped_cache()
+    plans = {}
+    for name, G in sets.items():
+        p = autotune.plan_for(G, max_batch[name], table)
+        if p is not None:
+            plans[name] = p
 
     # batched service rate of each set alone (full batches back to back) -> capacity of the mix
     rate = {}
@@ -271,12 +279,13 @@ def serve_benchmark(n_requests: int = 4000, loads=(0.5, 0.8), slots: int = 2, bu
         b = max_batch[name]
         d = torch.stack([payloads[name][i % pool] for i in range(b)])
         out = torch.empty((b, 2, G.ell, G.n), dtype=torch.int64, device="cuda")
-        ws = G.workspace(b)
-        G.keyswitch(d, evks[name], out, b, ws)
+        plan = plans.get(name)
+        ws = G.workspace(b, plan)
+        G.keyswitch(d, evks[name], out, b, ws, plan)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(5):
-            G.keyswitch(d, evks[name], out, b, ws)
+            G.keyswitch(d, evks[name], out, b, ws, plan)
         torch.cuda.synchronize()
         rate[name] = 5 * b / (time.perf_counter() - t0)
         del d, out, ws
@@ -284,6 +293,7 @@ def serve_benchmark(n_requests: int = 4000, loads=(0.5, 0.8), slots: int = 2, bu
 
     names = list(SERVE_SETS)
     result = {"capacity_req_per_s": round(capacity, 1), "set_rates_ks_per_s": {k: round(v, 1) for k, v in rate.items()},
+              "plans": {k: repr(v) for k, v in plans.items()},
               "requests": n_requests, "slots": slots, "runs": []}
     for load in loads:
         lam = load * capacity
@@ -292,7 +302,7 @@ def serve_benchmark(n_requests: int = 4000, loads=(0.5, 0.8), slots: int = 2, bu
         row = {"load": load, "rate_req_per_s": round(lam, 1)}
         for mode, mb, sl in (("batched", max_batch, slots), ("unbatched", {k: 1 for k in names}, 1)):
             reqs = [Request(i, picks[i], payloads[picks[i]][i % pool]) for i in range(n_requests)]
-            ex = GpuExecutor(sets, evks, slots=sl)
+            ex = GpuExecutor(sets, evks, plans if mode == "batched" else {}, slots=sl)
             sched = Scheduler(ex, int(budget_gb * (1 << 30)), mb, slots=sl)
             sched.run(reqs, offs)
             torch.cuda.synchronize()

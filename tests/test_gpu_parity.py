@@ -120,6 +120,8 @@ def _plans(ks, P, log_n):
             plans.append(ks.make_plan(df, chunks, log_r))
             if log_r <= 4:  # the int8-MFMA BConv
                 plans.append(ks.make_plan(df, chunks, log_r, mfma=True))
+            # the batch over two streams (3 items: 1 + 2)
+            plans.append(ks.make_plan(df, chunks, log_r, mfma=log_r <= 4, split=True))
     return plans
 
 
@@ -158,7 +160,7 @@ def test_keyswitch_benchmark_sizes(ks, name):
     dd, ee = dev(d), dev(evk)
     plans = [None, ks.make_plan(ks.DSOB), ks.make_plan(ks.DPOC, 4), ks.make_plan(ks.DSOC, 2),
              ks.make_plan(ks.DPOB, 1, 4, mfma=True), ks.make_plan(ks.DSOC, 3, 3, mfma=True),
-             ks.make_plan(ks.STAGED, 1, 4, mfma=True)]
+             ks.make_plan(ks.STAGED, 1, 4, mfma=True), ks.make_plan(ks.DPOB, 1, 4, mfma=True, split=True)]
     for plan in plans:
         out = empty(ref.shape)
         ws = G.workspace(batch, plan)
@@ -290,3 +292,8 @@ def test_launch_counts_follow_table_iii(ks):
     assert G8.launch_count(1, ks.make_plan(ks.DPOB)) == G.launch_count(1, ks.make_plan(ks.DPOB))
     assert G8.launch_count(1, ks.make_plan(ks.DSOB)) > G.launch_count(1, ks.make_plan(ks.DSOB))
     assert G.launch_count(1, ks.make_plan(ks.DPOC, 6)) > G.launch_count(1, ks.make_plan(ks.DPOC, 3))
+    # a split batch runs each plan twice (once per half), a batch of one is not split
+    sp = ks.make_plan(ks.DPOB, split=True)
+    assert G.launch_count(4, sp) == 2 * G.launch_count(4, ks.make_plan(ks.DPOB))
+    assert G.launch_count(1, sp) == G.launch_count(1, ks.make_plan(ks.DPOB))
+    assert G.workspace_bytes(5, sp) == G.workspace_bytes(2) + G.workspace_bytes(3)

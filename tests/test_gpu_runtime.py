@@ -20,13 +20,17 @@ def ks():
     return k
 
 
-@pytest.mark.parametrize("dnum,log_n,ell,batch,df", [(2, 15, 10, 4, 1), (4, 16, 32, 2, 1), (2, 13, 6, 1, 0),
-                                                      (3, 12, 7, 3, 3)])
-def test_graph_replay_matches_eager(ks, dnum, log_n, ell, batch, df):
+@pytest.mark.parametrize("dnum,log_n,ell,batch,df,flags", [(2, 15, 10, 4, 1, 0), (4, 16, 32, 2, 1, 0),
+                                                            (2, 13, 6, 1, 0, 0), (3, 12, 7, 3, 3, 0),
+                                                            (2, 15, 10, 4, 1, 3), (3, 12, 7, 3, 4, 2)])
+def test_graph_replay_matches_eager(ks, dnum, log_n, ell, batch, df, flags):
+    """Replays of a captured KeySwitch equal eager calls; flags 2 (a batch
+    split over two streams) captures a fork and a join of the second stream."""
     G = ks.KsParams(dnum, log_n, ell)
     P = oracle.Params(dnum, log_n, ell)
     _, _, evk = oracle.keygen(P, h=64)
-    plan = ks.make_plan(df, 2 if df in (ks.DSOC, ks.DPOC) else 1)
+    plan = ks.make_plan(df, 2 if df in (ks.DSOC, ks.DPOC) else 1, 3 if flags & 1 else -1,
+                        mfma=bool(flags & 1), split=bool(flags & 2))
     ee = dev(evk)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
