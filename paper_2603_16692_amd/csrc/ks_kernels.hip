@@ -134,7 +134,7 @@ __global__ __launch_bounds__(TC) void k_cols(DevTables tb, uint64_t* x, int firs
 // Forward: Q canonical in; P [0, 4q) in; canonical out. Inverse: canonical in;
 // out Q canonical, P [0, 2q); times N^-1 (canonical) when `scale` is set.
 template <int LOGM, int LOGE, bool INV>
-__global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_blocks(DevTables tb, const uint64_t* src, uint64_t* dst,
+__global__ __launch_bounds__((1 << (LOGM - LOGE)), LOGM >= 12 ? 4 : 1) void k_blocks(DevTables tb, const uint64_t* src, uint64_t* dst,
                                                                  int first, int nlimbs, int items, int scale) {
   using B = BlockNtt<LOGM, LOGE>;
   extern __shared__ uint64_t lds[];
@@ -554,7 +554,7 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
       }
       const uint64_t* k0 = evk + (((size_t)j * 2 + 0) * nl + t) * N + boff;
       const uint64_t* k1 = evk + (((size_t)j * 2 + 1) * nl + t) * N + boff;
-      // |v| <= 2q, key < q: each product is within 1.25q; fold every 4 digits
+      // |v| <= 2.2q, key < q: each product is within 1.33q; fold every 4 digits
 #pragma unroll
       for (int i = 0; i < B::E; ++i) {
         const int x = B::cl_pos(tid, i);
@@ -817,7 +817,7 @@ __device__ __forceinline__ void stage_twiddles(T* tw, const T* table, uint32_t B
 //   s_c = -NTT(t2_c) + sum_{j in [j0, j1)} ext_j * evk[j][c],
 //   ext_j = d (i in D_j) or the forward block pass of ext1 slot j,
 //   out_c = s_c * P^-1 (canonical).
-// t2 and ext1 canonical in, |values| <= 2q inside. Inputs and key blocks are
+// t2 and ext1 canonical in, |values| <= 2.2q inside. Inputs and key blocks are
 // loaded before the transform that precedes their use, so that their latency
 // overlaps it.
 template <int LOGM, int LOGE>
