@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--batch", type=int, default=0, help="override the workload's batch size")
+    ap.add_argument("--level", type=int, default=0,
+                    help="KeySwitch at this many Q limbs with the top-level key (default: the top level)")
     ap.add_argument("--plan", default="",
                     help="dataflow[,chunks[,log_r[,options]]], options mfma and/or split joined by '+', "
                          "e.g. DPOB or DSOC,2,3 or DPOB,1,4,mfma+split")
@@ -154,7 +156,10 @@ def main():
         batch = args.batch
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
-    G = ks.KsParams(dnum, log_n, ell)
+    top = ks.KsParams(dnum, log_n, ell)
+    G = top.at_level(args.level) if args.level else top
+    if args.level:
+        desc += f" at level {args.level}"
 
     plan = None
     if args.plan:
@@ -166,9 +171,10 @@ def main():
         plan = ks.make_plan(df, chunks, log_r, "mfma" in opts, "split" in opts)
 
     to_dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda")
-    d = to_dev(ciphertext_batch(G.moduli[:ell], G.n, batch))
-    evk = to_dev(uniform_key(G.moduli, G.n, G.ndig))
-    out = torch.empty((batch, 2, ell, G.n), dtype=torch.int64, device="cuda")
+    lv = G.ell
+    d = to_dev(ciphertext_batch(G.moduli[:lv], G.n, batch))
+    evk = to_dev(uniform_key(top.moduli, top.n, top.ndig))  # the top-level key
+    out = torch.empty((batch, 2, lv, G.n), dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
 
     tuning = None
@@ -283,14 +289,15 @@ def main():
                     "launches_per_step": per_step, "algorithmic_bytes_per_launch": int(per_launch)}
 
     # algorithmic bytes of the whole KeySwitch: d + out + evk / batch
-    ks_bytes = (ell * G.n * 8) + (2 * ell * G.n * 8) + (2 * G.ndig * G.nl * G.n * 8) / batch
+    ks_bytes = (lv * G.n * 8) + (2 * lv * G.n * 8) + (2 * G.ndig * G.nl * G.n * 8) / batch
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        P = oracle.Params(dnum, log_n, ell)
+        top_p = oracle.Params(dnum, log_n, ell)
+        P = top_p.at_level(lv)
         dh = ciphertext_batch(P.q, P.n, 1)
-        kh = uniform_key(P.moduli, P.n, P.ndig)
+        kh = uniform_key(top_p.moduli, P.n, top_p.ndig)
         n_done, t_start = 0, time.perf_counter()
         while True:
             oracle.keyswitch(P, dh, kh, 1)
@@ -307,7 +314,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": desc, "dnum": dnum, "N": G.n, "L": ell, "k": G.k, "batch": batch,
+        "config": {"workload": desc, "dnum": dnum, "N": G.n, "L": ell, "level": lv, "k": G.k, "batch": batch,
                    "plan": repr(plan), "launches_per_step": len(kinds)},
         "plain_single_ks_per_s": round(plain, 2) if plain else None,
         "graph_ks_per_s": round(graph_rate, 2) if graph_rate else None,

@@ -100,6 +100,7 @@ typedef struct {
 
 typedef struct {
   int n, log_n, ell, k, alpha, dnum, ndig;
+  int key_ell; /* Q limbs of the evaluation key: ell, or the top level's for a handle of ks_params_at_level */
   uint64_t moduli[KS_MAX_LIMBS]; /* q_0..q_{ell-1}, p_0..p_{k-1} */
   uint64_t psi[KS_MAX_LIMBS];
 } ks_info;
@@ -111,6 +112,22 @@ typedef struct {
  * Synchronous (it uploads tables). */
 int ks_params_create(int dnum, int log_n, int ell, ks_params** out);
 void ks_params_destroy(ks_params* p);
+
+/* The same parameter set at level `level` (1 <= level <= ell of `top`): a
+ * ciphertext that has lost its last ell - level limbs, KeySwitched with the
+ * top level's evaluation key (the level-aware KeySwitch, which the paper's
+ * discussion names as the first way to exploit its per-parameter findings:
+ * the work and footprint shrink with the level, so the best plan can change).
+ * The level keeps top's P primes, k and alpha; Q becomes q_0..q_{level-1};
+ * the digits are top's digits cut at `level` (ndig = ceil(level/alpha)). Every
+ * call on the new handle takes and returns data at the level (d [B][level][N],
+ * out [B][2][level][N], ext and acc over level + k limbs) but reads the
+ * evaluation key in the top level's layout [ndig_top][2][ell_top + k][N]
+ * (limb t < level at row t, p_m at row ell_top + m). The new handle is
+ * independent of `top` (destroy each with ks_params_destroy). KS_EINVAL for
+ * a level outside [1, ell]. ks_bconv on a level handle converts between the
+ * level's digits / P and the level's limbs. */
+int ks_params_at_level(const ks_params* top, int level, ks_params** out);
 
 /* Host copy of the derived parameters. */
 int ks_params_info(const ks_params* p, ks_info* info);

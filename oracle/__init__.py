@@ -56,6 +56,11 @@ def lib():
         L.orc_keygen.argtypes = [c_int, c_int, c_int, c_int, c_u64, c_u64, c_u64, c_u64, c_int,
                                  _i8p, _i8p, _u64p]
         L.orc_ks_error.argtypes = [c_int, c_int, c_int, _u64p, _u64p, _i8p, _i8p, _i64p, c_int]
+        L.orc_modup_level.argtypes = [c_int, c_int, c_int, c_int, _u64p, _u64p, c_int]
+        L.orc_keymult_level.argtypes = [c_int, c_int, c_int, c_int, _u64p, _u64p, _u64p, c_int]
+        L.orc_moddown_level.argtypes = [c_int, c_int, c_int, c_int, _u64p, _u64p, c_int]
+        L.orc_keyswitch_level.argtypes = [c_int, c_int, c_int, c_int, _u64p, _u64p, _u64p, c_int]
+        L.orc_ks_error_level.argtypes = [c_int, c_int, c_int, c_int, _u64p, _u64p, _i8p, _i8p, _i64p, c_int]
         L.orc_max_threads.restype = c_int
         L.orc_set_threads.argtypes = [c_int]
         _lib = L
@@ -63,28 +68,44 @@ def lib():
 
 
 class Params:
-    """Parameters of one (dnum, N, ell) set as the oracle derives them."""
+    """Parameters of one (dnum, N, ell) set as the oracle derives them, at
+    level `level` (default: the top level ell).
 
-    def __init__(self, dnum: int, log_n: int, ell: int):
+    At a level l < ell the KeySwitch keeps the top level's P, k and alpha and
+    works over q_0..q_{l-1} with the digits cut at l, using the top-level key
+    (shape key_shape); ell, q, moduli, nl and ndig describe the level."""
+
+    def __init__(self, dnum: int, log_n: int, ell: int, level: int = None):
         mod = np.zeros(256, dtype=np.uint64)
         psi = np.zeros(256, dtype=np.uint64)
         info = np.zeros(5, dtype=np.int64)
         if lib().orc_derive(dnum, log_n, ell, mod, psi, info) != 0:
             raise ValueError(f"invalid parameters dnum={dnum} log_n={log_n} ell={ell}")
-        self.dnum, self.log_n, self.ell = dnum, log_n, ell
-        self.n, _, self.k, self.alpha, self.ndig = (int(v) for v in info)
-        self.nl = self.ell + self.k
-        self.moduli = [int(v) for v in mod[: self.nl]]
-        self.psi = [int(v) for v in psi[: self.nl]]
+        level = ell if level is None else level
+        if not 1 <= level <= ell:
+            raise ValueError(f"level {level} outside [1, {ell}]")
+        self.dnum, self.log_n, self.top_ell, self.ell = dnum, log_n, ell, level
+        self.n, _, self.k, self.alpha, top_ndig = (int(v) for v in info)
+        top_mod = [int(v) for v in mod[: ell + self.k]]
+        top_psi = [int(v) for v in psi[: ell + self.k]]
+        self.moduli = top_mod[:level] + top_mod[ell:]
+        self.psi = top_psi[:level] + top_psi[ell:]
+        self.nl = level + self.k
+        self.ndig = -(-level // self.alpha)
+        self.key_shape = (top_ndig, 2, ell + self.k, self.n)
         self.q = self.moduli[: self.ell]
         self.p = self.moduli[self.ell:]
+
+    def at_level(self, level: int) -> "Params":
+        return Params(self.dnum, self.log_n, self.top_ell, level)
 
     def digit(self, j: int):
         lo = j * self.alpha
         return list(range(lo, min(lo + self.alpha, self.ell)))
 
     def __repr__(self):
-        return f"Params(dnum={self.dnum}, N=2^{self.log_n}, ell={self.ell}, k={self.k})"
+        lv = f", level={self.ell}" if self.ell != self.top_ell else ""
+        return f"Params(dnum={self.dnum}, N=2^{self.log_n}, ell={self.top_ell}{lv}, k={self.k})"
 
 
 def _c(a):
@@ -119,6 +140,8 @@ def intt(q: int, psi: int, log_n: int, a) -> np.ndarray:
 def bconv(P: Params, src_set: int, src, batch: int = 1) -> np.ndarray:
     """Fast base conversion; src_set = digit j (-> PQ minus D_j) or -1 (P -> Q)."""
     src = _c(src)
+    if P.ell != P.top_ell:
+        raise ValueError("bconv is defined here for the top level only")
     if src_set < 0:
         nd = P.ell
     else:
@@ -131,28 +154,34 @@ def bconv(P: Params, src_set: int, src, batch: int = 1) -> np.ndarray:
 
 def modup(P: Params, d, batch: int) -> np.ndarray:
     ext = np.zeros((batch, P.ndig, P.nl, P.n), dtype=np.uint64)
-    if lib().orc_modup(P.dnum, P.log_n, P.ell, _c(d), ext, batch) != 0:
+    if lib().orc_modup_level(P.dnum, P.log_n, P.top_ell, P.ell, _c(d), ext, batch) != 0:
         raise ValueError("modup")
     return ext
 
 
 def keymult(P: Params, ext, evk, batch: int) -> np.ndarray:
+    """evk: the top-level key (P.key_shape)."""
     acc = np.zeros((batch, 2, P.nl, P.n), dtype=np.uint64)
-    if lib().orc_keymult(P.dnum, P.log_n, P.ell, _c(ext), _c(evk), acc, batch) != 0:
+    if lib().orc_keymult_level(P.dnum, P.log_n, P.top_ell, P.ell, _c(ext), _c(evk), acc, batch) != 0:
         raise ValueError("keymult")
     return acc
 
 
 def moddown(P: Params, acc, batch: int) -> np.ndarray:
     out = np.zeros((batch, 2, P.ell, P.n), dtype=np.uint64)
-    if lib().orc_moddown(P.dnum, P.log_n, P.ell, _c(acc), out, batch) != 0:
+    if lib().orc_moddown_level(P.dnum, P.log_n, P.top_ell, P.ell, _c(acc), out, batch) != 0:
         raise ValueError("moddown")
     return out
 
 
 def keyswitch(P: Params, d, evk, batch: int) -> np.ndarray:
+    """evk: the top-level key (P.key_shape); d and the output at level P.ell."""
     out = np.zeros((batch, 2, P.ell, P.n), dtype=np.uint64)
-    if lib().orc_keyswitch(P.dnum, P.log_n, P.ell, _c(d), _c(evk), out, batch) != 0:
+    if P.ell == P.top_ell:
+        rc = lib().orc_keyswitch(P.dnum, P.log_n, P.ell, _c(d), _c(evk), out, batch)
+    else:
+        rc = lib().orc_keyswitch_level(P.dnum, P.log_n, P.top_ell, P.ell, _c(d), _c(evk), out, batch)
+    if rc != 0:
         raise ValueError("keyswitch")
     return out
 
@@ -161,8 +190,8 @@ def keygen(P: Params, h: int = 64, seeds=(1, 2, 3, 4), noiseless: bool = False):
     """(s, s2, evk): ternary secrets with h nonzeros and the key from s to s2."""
     s = np.zeros(P.n, dtype=np.int8)
     s2 = np.zeros(P.n, dtype=np.int8)
-    evk = np.zeros((P.ndig, 2, P.nl, P.n), dtype=np.uint64)
-    rc = lib().orc_keygen(P.dnum, P.log_n, P.ell, h, seeds[0], seeds[1], seeds[2], seeds[3],
+    evk = np.zeros(P.key_shape, dtype=np.uint64)  # the key is made at the top level
+    rc = lib().orc_keygen(P.dnum, P.log_n, P.top_ell, h, seeds[0], seeds[1], seeds[2], seeds[3],
                           int(noiseless), s, s2, evk)
     if rc != 0:
         raise ValueError("keygen")
@@ -173,8 +202,8 @@ def ks_error(P: Params, d, out, s, s2, batch: int):
     """(agree, err): err[b] is the decryption error of KS output b under s2
     against d*s, as centered integers; agree says every limb gives the same."""
     err = np.zeros((batch, P.n), dtype=np.int64)
-    rc = lib().orc_ks_error(P.dnum, P.log_n, P.ell, _c(d), _c(out), np.ascontiguousarray(s, np.int8),
-                            np.ascontiguousarray(s2, np.int8), err, batch)
+    rc = lib().orc_ks_error_level(P.dnum, P.log_n, P.top_ell, P.ell, _c(d), _c(out),
+                                  np.ascontiguousarray(s, np.int8), np.ascontiguousarray(s2, np.int8), err, batch)
     if rc < 0:
         raise ValueError("ks_error")
     return bool(rc), err

@@ -22,7 +22,12 @@
  *   - psi is the smallest primitive 2N-th root of unity mod each prime;
  *   - NTT(a)[t] = sum_i a_i psi^(i*(2*brv(t)+1)) (bit-reversed evaluation order);
  *   - BConv is the fast (uncorrected) conversion with y_i in [0, q_i);
- *   - ModDown ends with (acc_Q - conv) * P^-1, without a rounding offset.
+ *   - ModDown ends with (acc_Q - conv) * P^-1, without a rounding offset;
+ *   - at a level l < ell (a ciphertext that has lost its last ell - l
+ *     limbs), the KeySwitch keeps the top level's P and alpha, works over
+ *     q_0..q_{l-1}, uses the digits D_j restricted to those limbs
+ *     (ceil(l / alpha) of them) and the top-level key restricted to the limbs
+ *     of q_0..q_{l-1} and P (the `_level` entry points).
  *
  * Layouts (all uint64, canonical residues, coefficient index fastest):
  *   d   [batch][ell][N]              over q_0..q_{ell-1}, NTT form
@@ -166,6 +171,37 @@ static int digit_lo(const orc_params* p, int j) { return j * p->alpha; }
 static int digit_hi(const orc_params* p, int j) {
   int h = (j + 1) * p->alpha;
   return h < p->ell ? h : p->ell;
+}
+
+/* Parameters of level `level` of the (dnum, N, ell) set: Q shrinks to its
+ * first `level` primes, P, k and alpha stay, the digits are those of the
+ * top level cut at `level`. */
+static int derive_level(int dnum, int log_n, int ell, int level, orc_params* p) {
+  if (derive(dnum, log_n, ell, p) != 0 || level < 1 || level > ell) return -1;
+  for (int m = 0; m < p->k; ++m) {
+    p->mod[level + m] = p->mod[ell + m];
+    p->psi[level + m] = p->psi[ell + m];
+  }
+  p->ell = level;
+  p->ndig = (level + p->alpha - 1) / p->alpha;
+  return 0;
+}
+
+/* The top-level key [ndig_top][2][ell+k][N] restricted to the limbs of level
+ * p->ell: [p->ndig][2][p->ell+k][N] (newly allocated). */
+static uint64_t* key_at_level(const orc_params* p, int ell_top, const uint64_t* evk) {
+  size_t n = p->n;
+  int nl = p->ell + p->k, nlt = ell_top + p->k;
+  uint64_t* key = (uint64_t*)malloc((size_t)p->ndig * 2 * nl * n * sizeof(uint64_t));
+  if (!key) return NULL;
+  for (int j = 0; j < p->ndig; ++j)
+    for (int c = 0; c < 2; ++c)
+      for (int t = 0; t < nl; ++t) {
+        int row = t < p->ell ? t : ell_top + (t - p->ell);
+        memcpy(key + (((size_t)j * 2 + c) * nl + t) * n, evk + (((size_t)j * 2 + c) * nlt + row) * n,
+               n * sizeof(uint64_t));
+      }
+  return key;
 }
 
 /* ------------------------------------------------------------------ NTT */
@@ -427,6 +463,59 @@ int orc_keyswitch(int dnum, int log_n, int ell, const uint64_t* d, const uint64_
   return 0;
 }
 
+/* The same steps at level `level` (1 <= level <= ell), with the key of the
+ * top level: d [batch][level][N], ext [batch][ceil(level/alpha)][level+k][N],
+ * evk [ndig_top][2][ell+k][N], acc [batch][2][level+k][N],
+ * out [batch][2][level][N]. level = ell gives the top-level functions. */
+int orc_modup_level(int dnum, int log_n, int ell, int level, const uint64_t* d, uint64_t* ext, int batch) {
+  orc_params p;
+  if (derive_level(dnum, log_n, ell, level, &p) != 0) return -1;
+  size_t dsz = (size_t)p.ell * p.n, esz = (size_t)p.ndig * (p.ell + p.k) * p.n;
+  for (int b = 0; b < batch; ++b) modup_one(&p, d + b * dsz, ext + b * esz);
+  return 0;
+}
+
+int orc_keymult_level(int dnum, int log_n, int ell, int level, const uint64_t* ext, const uint64_t* evk,
+                      uint64_t* acc, int batch) {
+  orc_params p;
+  if (derive_level(dnum, log_n, ell, level, &p) != 0) return -1;
+  uint64_t* key = key_at_level(&p, ell, evk);
+  if (!key) return -2;
+  size_t esz = (size_t)p.ndig * (p.ell + p.k) * p.n, asz = (size_t)2 * (p.ell + p.k) * p.n;
+  for (int b = 0; b < batch; ++b) keymult_one(&p, ext + b * esz, key, acc + b * asz);
+  free(key);
+  return 0;
+}
+
+int orc_moddown_level(int dnum, int log_n, int ell, int level, const uint64_t* acc, uint64_t* out, int batch) {
+  orc_params p;
+  if (derive_level(dnum, log_n, ell, level, &p) != 0) return -1;
+  size_t asz = (size_t)2 * (p.ell + p.k) * p.n, osz = (size_t)2 * p.ell * p.n;
+  for (int b = 0; b < batch; ++b) moddown_one(&p, acc + b * asz, out + b * osz);
+  return 0;
+}
+
+int orc_keyswitch_level(int dnum, int log_n, int ell, int level, const uint64_t* d, const uint64_t* evk,
+                        uint64_t* out, int batch) {
+  orc_params p;
+  if (derive_level(dnum, log_n, ell, level, &p) != 0) return -1;
+  size_t nl = (size_t)(p.ell + p.k);
+  size_t dsz = (size_t)p.ell * p.n, osz = (size_t)2 * p.ell * p.n;
+  uint64_t* key = key_at_level(&p, ell, evk);
+  uint64_t* ext = (uint64_t*)malloc((size_t)p.ndig * nl * p.n * sizeof(uint64_t));
+  uint64_t* acc = (uint64_t*)malloc(2 * nl * p.n * sizeof(uint64_t));
+  if (!key || !ext || !acc) { free(key); free(ext); free(acc); return -2; }
+  for (int b = 0; b < batch; ++b) {
+    modup_one(&p, d + b * dsz, ext);
+    keymult_one(&p, ext, key, acc);
+    moddown_one(&p, acc, out + b * osz);
+  }
+  free(key);
+  free(ext);
+  free(acc);
+  return 0;
+}
+
 /* ---------------------------------------------------------------- keygen */
 
 /* Ternary secret with exactly h nonzeros: positions by a partial
@@ -520,10 +609,10 @@ int orc_keygen(int dnum, int log_n, int ell, int h, uint64_t seed_s, uint64_t se
  * e_i = INTT(out0 + out1*NTT(s2) - d*NTT(s)), read as centered residues.
  * err [batch][N] receives the limb-0 centered values; the return value is 1 if
  * every limb holds the same integer at every coefficient, 0 if not, <0 on error. */
-int orc_ks_error(int dnum, int log_n, int ell, const uint64_t* d, const uint64_t* out, const int8_t* s,
-                 const int8_t* s2, int64_t* err, int batch) {
+int orc_ks_error_level(int dnum, int log_n, int ell, int level, const uint64_t* d, const uint64_t* out,
+                       const int8_t* s, const int8_t* s2, int64_t* err, int batch) {
   orc_params p;
-  if (derive(dnum, log_n, ell, &p) != 0) return -1;
+  if (derive_level(dnum, log_n, ell, level, &p) != 0) return -1;
   size_t n = p.n;
   int agree = 1;
   for (int b = 0; b < batch; ++b) {
@@ -552,4 +641,9 @@ int orc_ks_error(int dnum, int log_n, int ell, const uint64_t* d, const uint64_t
     }
   }
   return agree;
+}
+
+int orc_ks_error(int dnum, int log_n, int ell, const uint64_t* d, const uint64_t* out, const int8_t* s,
+                 const int8_t* s2, int64_t* err, int batch) {
+  return orc_ks_error_level(dnum, log_n, ell, ell, d, out, s, s2, err, batch);
 }

@@ -62,6 +62,27 @@ class TinyParams:
         lo = j * self.alpha
         return list(range(lo, min(lo + self.alpha, self.ell)))
 
+    def at_level(self, level: int) -> "TinyParams":
+        """The set at `level` Q limbs: the first `level` primes of Q, the same
+        P, k and alpha, the digits cut at `level`."""
+        L = TinyParams.__new__(TinyParams)
+        L.__dict__.update(self.__dict__)
+        L.top_ell = self.ell
+        L.ell = level
+        L.q = self.q[:level]
+        L.moduli = L.q + L.p
+        L.psi = self.psi[:level] + self.psi[self.ell:]
+        L.nl = len(L.moduli)
+        L.ndig = -(-level // self.alpha)
+        return L
+
+
+def key_at_level(top: TinyParams, L: TinyParams, evk):
+    """The top-level key restricted to the limbs of level L: digits j < L.ndig,
+    rows of q_0..q_{level-1} and of P."""
+    rows = list(range(L.ell)) + [top.ell + m for m in range(top.k)]
+    return [[[list(evk[j][c][r]) for r in rows] for c in range(2)] for j in range(L.ndig)]
+
 
 def ntt_def(a, q: int, psi: int, log_n: int):
     """NTT(a)[t] = sum_i a_i * psi^(i*(2*brv(t)+1)) mod q."""

@@ -47,12 +47,13 @@ class Plan(ctypes.Structure):
 
 class Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("log_n", ctypes.c_int), ("ell", ctypes.c_int), ("k", ctypes.c_int),
-                ("alpha", ctypes.c_int), ("dnum", ctypes.c_int), ("ndig", ctypes.c_int),
+                ("alpha", ctypes.c_int), ("dnum", ctypes.c_int), ("ndig", ctypes.c_int), ("key_ell", ctypes.c_int),
                 ("moduli", ctypes.c_uint64 * KS_MAX_LIMBS), ("psi", ctypes.c_uint64 * KS_MAX_LIMBS)]
 
 
 _vp, _i, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
 _lib.ks_params_create.argtypes = [_i, _i, _i, ctypes.POINTER(_vp)]
+_lib.ks_params_at_level.argtypes = [_vp, _i, ctypes.POINTER(_vp)]
 _lib.ks_params_destroy.argtypes = [_vp]
 _lib.ks_params_destroy.restype = None
 _lib.ks_params_info.argtypes = [_vp, ctypes.POINTER(Info)]
@@ -81,7 +82,7 @@ _lib.ks_graph_destroy.restype = None
 KIND_NAMES = ["intt_d_blocks", "modup_cols", "keymult_blocks", "moddown_cols", "moddown_blocks", "ext_blocks",
               "pblocks_inv", "copy_digits", "keymult", "bconv", "ntt"]
 
-EXPORTED = ["ks_params_create", "ks_params_destroy", "ks_params_info", "ks_workspace_bytes", "ks_default_plan",
+EXPORTED = ["ks_params_create", "ks_params_destroy", "ks_params_at_level", "ks_params_info", "ks_workspace_bytes", "ks_default_plan",
             "ks_ntt", "ks_intt", "ks_bconv", "ks_modup", "ks_keymult", "ks_moddown", "ks_keyswitch",
             "ks_launch_count", "ks_strerror", "ks_last_hip_error", "ks_trace_begin", "ks_trace_end",
             "ks_graph_create", "ks_graph_launch", "ks_graph_destroy"]
@@ -124,19 +125,31 @@ def make_plan(dataflow=DPOB, chunks=1, log_r=-1, mfma=False, split=False):
 
 
 class KsParams:
-    """Handle of one (dnum, N = 2^log_n, ell) parameter set on the current device."""
+    """Handle of one (dnum, N = 2^log_n, ell) parameter set on the current
+    device, or of one of its levels (at_level)."""
 
-    def __init__(self, dnum: int, log_n: int, ell: int):
+    def __init__(self, dnum: int, log_n: int, ell: int, _handle=None):
         h = _vp()
-        _check(_lib.ks_params_create(dnum, log_n, ell, ctypes.byref(h)), "ks_params_create")
+        if _handle is None:
+            _check(_lib.ks_params_create(dnum, log_n, ell, ctypes.byref(h)), "ks_params_create")
+        else:
+            h = _handle
         self._h = h
         info = Info()
         _check(_lib.ks_params_info(h, ctypes.byref(info)), "ks_params_info")
         self.n, self.log_n, self.ell, self.k = info.n, info.log_n, info.ell, info.k
         self.alpha, self.dnum, self.ndig = info.alpha, info.dnum, info.ndig
+        self.key_ell = info.key_ell
         self.nl = self.ell + self.k
         self.moduli = [int(info.moduli[t]) for t in range(self.nl)]
         self.psi = [int(info.psi[t]) for t in range(self.nl)]
+
+    def at_level(self, level: int) -> "KsParams":
+        """The same set at `level` Q limbs, KeySwitched with this set's
+        evaluation key (ks_params_at_level)."""
+        h = _vp()
+        _check(_lib.ks_params_at_level(self._h, level, ctypes.byref(h)), "ks_params_at_level")
+        return KsParams(self.dnum, self.log_n, level, _handle=h)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -145,7 +158,8 @@ class KsParams:
             self._h = None
 
     def __repr__(self):
-        return f"KsParams(dnum={self.dnum}, N=2^{self.log_n}, ell={self.ell}, k={self.k})"
+        lv = f", level of ell={self.key_ell}" if self.key_ell != self.ell else ""
+        return f"KsParams(dnum={self.dnum}, N=2^{self.log_n}, ell={self.ell}{lv}, k={self.k})"
 
     # ------------------------------------------------------------ queries
     def default_plan(self, batch: int = 1) -> Plan:
@@ -203,7 +217,8 @@ class KsParams:
     # ------------------------------------------------------------ helpers
     def shapes(self, batch: int):
         n, ell, nl, nd = self.n, self.ell, self.nl, self.ndig
-        return {"d": (batch, ell, n), "ext": (batch, nd, nl, n), "evk": (nd, 2, nl, n),
+        key_nd = -(-self.key_ell // self.alpha)
+        return {"d": (batch, ell, n), "ext": (batch, nd, nl, n), "evk": (key_nd, 2, self.key_ell + self.k, n),
                 "acc": (batch, 2, nl, n), "out": (batch, 2, ell, n)}
 
 

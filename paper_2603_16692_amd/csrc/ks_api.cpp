@@ -264,18 +264,9 @@ int run_fused(const ks_params* p, const ks_plan& plan, const uint64_t* d, const 
 
 extern "C" {
 
-int ks_params_create(int dnum, int log_n, int ell, ks_params** out) {
-  if (!out) return KS_ENULL;
-  *out = nullptr;
-  if (log_n < 3 || log_n > 17 || ell < 1 || dnum < 1 || dnum > ell) return KS_EINVAL;
-  const int alpha = (ell + dnum - 1) / dnum;
-  if (ell + alpha > KS_MAX_LIMBS) return KS_EINVAL;
-  ks_params* p = new (std::nothrow) ks_params;
-  if (!p) return KS_ENOMEM;
-  if (!ks::derive_params(dnum, log_n, ell, p->hp)) {
-    delete p;
-    return KS_EINVAL;
-  }
+// Uploads the tables of p->hp and creates the handle's stream and events;
+// destroys p on failure.
+static int finish_params(ks_params* p, ks_params** out) {
   std::vector<uint64_t> blob;
   ks::build_tables(p->hp, blob, p->tb);
   hipError_t e = hipGetDevice(&p->device);
@@ -319,6 +310,34 @@ int ks_params_create(int dnum, int log_n, int ell, ks_params** out) {
   return KS_OK;
 }
 
+int ks_params_create(int dnum, int log_n, int ell, ks_params** out) {
+  if (!out) return KS_ENULL;
+  *out = nullptr;
+  if (log_n < 3 || log_n > 17 || ell < 1 || dnum < 1 || dnum > ell) return KS_EINVAL;
+  const int alpha = (ell + dnum - 1) / dnum;
+  if (ell + alpha > KS_MAX_LIMBS) return KS_EINVAL;
+  ks_params* p = new (std::nothrow) ks_params;
+  if (!p) return KS_ENOMEM;
+  if (!ks::derive_params(dnum, log_n, ell, p->hp)) {
+    delete p;
+    return KS_EINVAL;
+  }
+  return finish_params(p, out);
+}
+
+int ks_params_at_level(const ks_params* top, int level, ks_params** out) {
+  if (!top || !out) return KS_ENULL;
+  *out = nullptr;
+  if (level < 1 || level > top->hp.ell) return KS_EINVAL;
+  ks_params* p = new (std::nothrow) ks_params;
+  if (!p) return KS_ENOMEM;
+  if (!ks::level_params(top->hp, level, p->hp)) {
+    delete p;
+    return KS_EINVAL;
+  }
+  return finish_params(p, out);
+}
+
 void ks_params_destroy(ks_params* p) {
   if (!p) return;
   if (p->side) (void)hipStreamDestroy(p->side);
@@ -338,6 +357,7 @@ int ks_params_info(const ks_params* p, ks_info* info) {
   info->alpha = p->hp.alpha;
   info->dnum = p->hp.dnum;
   info->ndig = p->hp.ndig;
+  info->key_ell = p->hp.key_ell;
   for (int t = 0; t < p->hp.nl; ++t) {
     info->moduli[t] = p->hp.mod[t];
     info->psi[t] = p->hp.psi[t];

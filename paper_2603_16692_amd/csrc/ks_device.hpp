@@ -66,7 +66,16 @@ struct DevTables {
   const uint64_t* up_mx;    // [ndig][up_ng][up_nm][64][2]
   const uint64_t* dn_mx;    // [dn_ng][dn_nm][64][2]
   int up_ng, up_nm, dn_ng, dn_nm;
+  // Rows of the evaluation key [ndig][2][evk_nl][N]: limb t < ell is row t,
+  // P limb ell + m is row evk_p0 + m. At the top level evk_nl = nl and
+  // evk_p0 = ell; at a lower level the key of the top level is read as is.
+  int evk_nl, evk_p0;
 };
+
+// Row of limb t of the extended basis in one (digit, component) slice of the key.
+__device__ __forceinline__ size_t key_row(const DevTables& tb, int j, int c, int t) {
+  return ((size_t)j * 2 + c) * tb.evk_nl + (t < tb.ell ? t : tb.evk_p0 + (t - tb.ell));
+}
 
 // ------------------------------------------------------------ integers
 

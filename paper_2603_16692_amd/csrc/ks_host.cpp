@@ -159,6 +159,21 @@ bool derive_params(int dnum, int log_n, int ell, HostParams& hp) {
   if (!largest_primes(50, step, ell, hp.mod)) return false;
   if (!largest_primes(60, step, hp.k, hp.mod)) return false;
   for (uint64_t q : hp.mod) hp.psi.push_back(smallest_root(q, hp.n));
+  hp.key_ell = ell;
+  return true;
+}
+
+bool level_params(const HostParams& top, int level, HostParams& hp) {
+  if (level < 1 || level > top.ell) return false;
+  hp = top;
+  hp.ell = level;
+  hp.ndig = (level + hp.alpha - 1) / hp.alpha;
+  hp.nl = level + hp.k;
+  hp.mod.assign(top.mod.begin(), top.mod.begin() + level);
+  hp.mod.insert(hp.mod.end(), top.mod.begin() + top.ell, top.mod.end());
+  hp.psi.assign(top.psi.begin(), top.psi.begin() + level);
+  hp.psi.insert(hp.psi.end(), top.psi.begin() + top.ell, top.psi.end());
+  hp.key_ell = top.key_ell;
   return true;
 }
 
@@ -372,6 +387,8 @@ void build_tables(const HostParams& hp, std::vector<uint64_t>& blob, DevTables& 
   tb.up_nm = up_nm;
   tb.dn_ng = dn_ng;
   tb.dn_nm = dn_nm;
+  tb.evk_nl = hp.key_ell + k;
+  tb.evk_p0 = hp.key_ell;
   auto atd = [](size_t o) { return reinterpret_cast<const double*>(o * sizeof(uint64_t)); };
   tb.twf_d = atd(o_twf_d);
   tb.twi_d = atd(o_twi_d);

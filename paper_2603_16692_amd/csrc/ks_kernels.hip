@@ -552,8 +552,8 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
         for (int i = 0; i < B::E; ++i) v[i] = u2d(src[B::fr_pos(tid, i)]);
         fwd_opaque<B>(A, v, ld, tid, B0);
       }
-      const uint64_t* k0 = evk + (((size_t)j * 2 + 0) * nl + t) * N + boff;
-      const uint64_t* k1 = evk + (((size_t)j * 2 + 1) * nl + t) * N + boff;
+      const uint64_t* k0 = evk + key_row(tb, j, 0, t) * N + boff;
+      const uint64_t* k1 = evk + key_row(tb, j, 1, t) * N + boff;
       // |v| <= 2.2q, key < q: each product is within 1.33q; fold every 4 digits
 #pragma unroll
       for (int i = 0; i < B::E; ++i) {
@@ -591,8 +591,8 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
 #pragma unroll
     for (int i = 0; i < B::E; ++i) v[i] = src[B::fr_pos(tid, i)];
     fwd_opaque<B>(A, v, lds, tid, B0);
-    const uint64_t* k0 = evk + (((size_t)j * 2 + 0) * nl + t) * N + boff;
-    const uint64_t* k1 = evk + (((size_t)j * 2 + 1) * nl + t) * N + boff;
+    const uint64_t* k0 = evk + key_row(tb, j, 0, t) * N + boff;
+    const uint64_t* k1 = evk + key_row(tb, j, 1, t) * N + boff;
 #pragma unroll
     for (int i = 0; i < B::E; ++i) {
       const int x = B::cl_pos(tid, i);
@@ -888,8 +888,8 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
 #pragma unroll
       for (int e = 0; e < B::E; ++e) cur[e] = nxt[e];
     }
-    const uint64_t* k0 = evk + (((size_t)j * 2 + 0) * nl + i) * N + boff;
-    const uint64_t* k1 = evk + (((size_t)j * 2 + 1) * nl + i) * N + boff;
+    const uint64_t* k0 = evk + key_row(tb, j, 0, i) * N + boff;
+    const uint64_t* k1 = evk + key_row(tb, j, 1, i) * N + boff;
     double w0[B::E], w1[B::E];
 #pragma unroll
     for (int e = 0; e < B::E; ++e) {
@@ -1017,7 +1017,7 @@ __global__ void k_keymult(DevTables tb, const uint64_t* ext, const uint64_t* evk
   const LimbC L = tb.limb[t];
   uint64_t s = 0;
   for (int j = 0; j < tb.ndig; ++j) {
-    s += mont_mul(ext[(((size_t)item * tb.ndig + j) * tb.nl + t) * N + x], evk[(((size_t)j * 2 + c) * tb.nl + t) * N + x],
+    s += mont_mul(ext[(((size_t)item * tb.ndig + j) * tb.nl + t) * N + x], evk[key_row(tb, j, c, t) * N + x],
                   L.q, L.mont_ninv);
     s = s >= L.two_q ? s - L.two_q : s;
   }
