@@ -29,6 +29,7 @@ WORKLOADS = {
     "c3": (8, 17, 56, 2, "deep-circuit KeySwitch (dnum,N,L)=(8,2^17,56), batch 2"),
 }
 HBM_PEAK_GBS = 8000.0
+OP_METRIC = {"keyswitch": "KeySwitch/s", "hmul": "HMUL/s", "hrot": "HROT/s"}
 
 # HBM bytes of one launch of the dominant kernel, from two rocprofv3 --pmc
 # runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
@@ -107,6 +108,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--batch", type=int, default=0, help="override the workload's batch size")
+    ap.add_argument("--op", default="keyswitch", choices=["keyswitch", "hmul", "hrot"],
+                    help="the timed operation: KeySwitch, or HMUL / HROT around it (same plan)")
     ap.add_argument("--level", type=int, default=0,
                     help="KeySwitch at this many Q limbs with the top-level key (default: the top level)")
     ap.add_argument("--plan", default="",
@@ -202,15 +205,26 @@ def main():
                   "default_ms": round(next((r["ms"] for r in results
                                             if tuple(r["plan"]) == G.default_plan(batch).key()), float("nan")), 4)}
     ws = G.workspace(batch, plan)
+    if args.op == "keyswitch":
+        step = lambda: G.keyswitch(d, evk, out, batch, ws, plan)
+    else:
+        # a second operand of the same shape; the key plays the relinearisation or rotation key
+        ews = G.eval_workspace(batch, plan)
+        ct = to_dev(ciphertext_batch(G.moduli[:lv], G.n, 2 * batch, seed_base=2000)).view(batch, 2, lv, G.n)
+        ct2 = to_dev(ciphertext_batch(G.moduli[:lv], G.n, 2 * batch, seed_base=3000)).view(batch, 2, lv, G.n)
+        if args.op == "hmul":
+            step = lambda: G.hmul(ct, ct2, evk, out, batch, ews, plan)
+        else:
+            step = lambda: G.hrot(ct, 5, evk, out, batch, ews, plan)
 
     for _ in range(args.warmup):
-        G.keyswitch(d, evk, out, batch, ws, plan)
+        step()
     torch.cuda.synchronize()
 
     # per-kernel breakdown of one step (untimed) -> the dominant kernel kind
     ev = ks.HipEvents(2 * 256)
     ks.trace_begin(ev)
-    G.keyswitch(d, evk, out, batch, ws, plan)
+    step()
     kinds = ks.trace_end()
     torch.cuda.synchronize()
     per_kind = {}
@@ -228,7 +242,7 @@ def main():
     t0 = time.perf_counter()
     step_ev.record(0, stream)
     for i in range(args.steps):
-        G.keyswitch(d, evk, out, batch, ws, plan)
+        step()
         step_ev.record(i + 1, stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -241,7 +255,7 @@ def main():
 
     # plain single-ciphertext path on the same parameters (default plan)
     plain = None
-    if batch > 1 and not args.no_plain:
+    if batch > 1 and not args.no_plain and args.op == "keyswitch":
         d1 = d[:1].contiguous()
         out1 = out[:1].contiguous()
         ws1 = G.workspace(1)
@@ -258,7 +272,7 @@ def main():
 
     # the same step replayed from a captured HIP graph
     graph_rate = None
-    if not args.no_graph:
+    if not args.no_graph and args.op == "keyswitch":
         gs = torch.cuda.Stream()
         gs.wait_stream(stream)
         with torch.cuda.stream(gs):
@@ -292,7 +306,7 @@ def main():
     ks_bytes = (lv * G.n * 8) + (2 * lv * G.n * 8) + (2 * G.ndig * G.nl * G.n * 8) / batch
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.op == "keyswitch":
         import oracle
         top_p = oracle.Params(dnum, log_n, ell)
         P = top_p.at_level(lv)
@@ -310,7 +324,7 @@ def main():
                "sample": f"{n_done} single-ciphertext KeySwitch(es) of the same parameter set, {el:.1f} s"}
 
     line = {
-        "metric": "KeySwitch/s", "value": round(value, 2), "unit": "KeySwitch/s", "n_gpus": 1,
+        "metric": OP_METRIC[args.op], "value": round(value, 2), "unit": OP_METRIC[args.op], "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
         "data": "synthetic",

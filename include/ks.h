@@ -171,6 +171,30 @@ int ks_moddown(const ks_params* p, const uint64_t* acc, uint64_t* out, int batch
 int ks_keyswitch(const ks_params* p, const uint64_t* d, const uint64_t* evk, uint64_t* out, int batch,
                  const ks_plan* plan, void* ws, void* stream);
 
+/* HMUL (Background section: the product of two ciphertexts followed by
+ * relinearisation): for a = (a0, a1) and b = (b0, b1), [batch][2][ell][N]
+ * canonical NTT form over the handle's Q (or level),
+ *   out = (a0*b0, a0*b1 + a1*b0) + KeySwitch(a1*b1),
+ * with evk the key from s*s to s (top-level layout, as ks_keyswitch). The
+ * KeySwitch runs under `plan` (NULL = default). ws: ks_eval_workspace_bytes
+ * bytes. out must not alias a or b. Asynchronous on `stream`. */
+int ks_hmul(const ks_params* p, const uint64_t* a, const uint64_t* b, const uint64_t* evk, uint64_t* out, int batch,
+            const ks_plan* plan, void* ws, void* stream);
+
+/* HROT (Background section: rotation of the slots) by the Galois element
+ * `galois` (odd, 0 < galois < 2N; the automorphism x -> x^galois): for
+ * ct = (c0, c1) [batch][2][ell][N],
+ *   out = (sigma(c0), 0) + KeySwitch(sigma(c1)),
+ * with evk the key from sigma(s) to s. In NTT form sigma permutes the slots:
+ * slot t of the image is slot t' of the input with
+ * 2 brv(t') + 1 = galois * (2 brv(t) + 1) mod 2N. KS_EINVAL for an even or
+ * out-of-range element. out must not alias ct. */
+int ks_hrot(const ks_params* p, const uint64_t* ct, int galois, const uint64_t* evk, uint64_t* out, int batch,
+            const ks_plan* plan, void* ws, void* stream);
+
+/* Workspace (bytes) of ks_hmul and ks_hrot: the KeySwitch's plus 3*batch*ell*N words. */
+int ks_eval_workspace_bytes(const ks_params* p, int batch, const ks_plan* plan, size_t* bytes);
+
 /* Number of kernel launches ks_keyswitch enqueues for (batch, plan). */
 int ks_launch_count(const ks_params* p, int batch, const ks_plan* plan);
 
@@ -200,6 +224,7 @@ void ks_graph_destroy(ks_graph* graph);
 #define KS_K_KEYMULT 8        /* ks_keymult element-wise kernel */
 #define KS_K_BCONV 9          /* ks_bconv */
 #define KS_K_NTT 10           /* ks_ntt / ks_intt passes */
+#define KS_K_EVAL 11          /* ks_hmul / ks_hrot element-wise passes */
 
 /* Launch trace (profiling; eager calls only, never under graph capture).
  * After ks_trace_begin, every kernel launch of a kind whose bit is set in

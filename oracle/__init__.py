@@ -61,6 +61,10 @@ def lib():
         L.orc_moddown_level.argtypes = [c_int, c_int, c_int, c_int, _u64p, _u64p, c_int]
         L.orc_keyswitch_level.argtypes = [c_int, c_int, c_int, c_int, _u64p, _u64p, _u64p, c_int]
         L.orc_ks_error_level.argtypes = [c_int, c_int, c_int, c_int, _u64p, _u64p, _i8p, _i8p, _i64p, c_int]
+        L.orc_keygen_pair.argtypes = [c_int, c_int, c_int, _i64p, _i64p, c_u64, c_u64, c_int, _u64p]
+        L.orc_automorph.argtypes = [c_u64, c_u64, c_int, _u64p, c_u64, _u64p, c_int]
+        L.orc_hmul_level.argtypes = [c_int, c_int, c_int, c_int, _u64p, _u64p, _u64p, _u64p, c_int]
+        L.orc_hrot_level.argtypes = [c_int, c_int, c_int, c_int, _u64p, c_u64, _u64p, _u64p, c_int]
         L.orc_max_threads.restype = c_int
         L.orc_set_threads.argtypes = [c_int]
         _lib = L
@@ -196,6 +200,70 @@ def keygen(P: Params, h: int = 64, seeds=(1, 2, 3, 4), noiseless: bool = False):
     if rc != 0:
         raise ValueError("keygen")
     return s, s2, evk
+
+
+def keygen_pair(P: Params, s_from, s_to, seeds=(3, 4), noiseless: bool = False) -> np.ndarray:
+    """The key from secret s_from to secret s_to (integer coefficient vectors),
+    made at the top level: for instance s_from = s*s (HMUL) or sigma_g(s) (HROT)."""
+    evk = np.zeros(P.key_shape, dtype=np.uint64)
+    a = np.ascontiguousarray(s_from, dtype=np.int64)
+    b = np.ascontiguousarray(s_to, dtype=np.int64)
+    if lib().orc_keygen_pair(P.dnum, P.log_n, P.top_ell, a, b, seeds[0], seeds[1], int(noiseless), evk) != 0:
+        raise ValueError("keygen_pair")
+    return evk
+
+
+def negacyclic_product(a, b) -> np.ndarray:
+    """Integer product of two coefficient vectors in Z[x]/(x^N + 1), by the
+    schoolbook sum over the nonzero coefficients of `a` (sparse secrets)."""
+    a = np.asarray(a, dtype=np.int64)
+    b = np.asarray(b, dtype=np.int64)
+    n = len(a)
+    out = np.zeros(n, dtype=np.int64)
+    for i in np.nonzero(a)[0]:
+        # a_i x^i * b: shift b by i, the part past x^N wraps with a sign change
+        out[i:] += a[i] * b[:n - i]
+        out[:i] -= a[i] * b[n - i:]
+    return out
+
+
+def automorph_coeffs(a, g: int) -> np.ndarray:
+    """a(x) -> a(x^g) on an integer coefficient vector (g odd)."""
+    a = np.asarray(a, dtype=np.int64)
+    n = len(a)
+    out = np.zeros(n, dtype=np.int64)
+    for i in range(n):
+        e = (i * g) % (2 * n)
+        if e < n:
+            out[e] += a[i]
+        else:
+            out[e - n] -= a[i]
+    return out
+
+
+def automorph(q: int, psi: int, log_n: int, a, g: int) -> np.ndarray:
+    """The automorphism x -> x^g of NTT-form limbs (rows of a), through the
+    coefficient domain."""
+    a = _c(a)
+    out = np.zeros_like(a)
+    lib().orc_automorph(q, psi, log_n, a, g, out, a.size >> log_n)
+    return out
+
+
+def hmul(P: Params, a, b, evk, batch: int) -> np.ndarray:
+    """(a0 b0, a0 b1 + a1 b0) + KS(a1 b1); a, b, out [batch][2][level][N]."""
+    out = np.zeros((batch, 2, P.ell, P.n), dtype=np.uint64)
+    if lib().orc_hmul_level(P.dnum, P.log_n, P.top_ell, P.ell, _c(a), _c(b), _c(evk), out, batch) != 0:
+        raise ValueError("hmul")
+    return out
+
+
+def hrot(P: Params, ct, g: int, evk, batch: int) -> np.ndarray:
+    """(sigma_g(c0), 0) + KS(sigma_g(c1)); ct, out [batch][2][level][N]."""
+    out = np.zeros((batch, 2, P.ell, P.n), dtype=np.uint64)
+    if lib().orc_hrot_level(P.dnum, P.log_n, P.top_ell, P.ell, _c(ct), g, _c(evk), out, batch) != 0:
+        raise ValueError("hrot")
+    return out
 
 
 def ks_error(P: Params, d, out, s, s2, batch: int):

@@ -554,21 +554,17 @@ static uint64_t signed_mod(int64_t v, uint64_t m) {
   return v >= 0 ? (uint64_t)v % m : (m - ((uint64_t)(-v) % m)) % m;
 }
 
-/* Evaluation key for switching from s to s2, one pair per digit j:
+/* Evaluation key for switching from secret s_from to secret s_to (both
+ * given by their integer coefficients), one pair per digit j:
  *   a_j uniform mod each t (draw (j*(ell+k)+t)*N + x of seed_a),
  *   e_j rounded Gaussian (seed_e, digit after digit),
- *   b_j = -a_j*s2 + e_j + [t in D_j] * [P]_t * s   (NTT form, per limb t).
- * s_out and s2_out receive the two ternary secrets (seeds seed_s, seed_s2).
+ *   b_j = -a_j*s_to + e_j + [t in D_j] * [P]_t * s_from   (NTT form, per limb t).
  * With noiseless != 0 every e_j is zero. */
-int orc_keygen(int dnum, int log_n, int ell, int h, uint64_t seed_s, uint64_t seed_s2, uint64_t seed_a,
-               uint64_t seed_e, int noiseless, int8_t* s_out, int8_t* s2_out, uint64_t* evk) {
-  orc_params p;
-  if (derive(dnum, log_n, ell, &p) != 0) return -1;
+static void make_key(const orc_params* pp, const int64_t* s_from, const int64_t* s_to, uint64_t seed_a,
+                     uint64_t seed_e, int noiseless, uint64_t* evk) {
+  const orc_params p = *pp;
   size_t n = p.n;
   int nl = p.ell + p.k;
-  if (h < 0 || (size_t)h > n) return -1;
-  ternary(seed_s, n, h, s_out);
-  ternary(seed_s2, n, h, s2_out);
   int64_t* e = (int64_t*)calloc((size_t)p.ndig * n, sizeof(int64_t));
   if (!noiseless) gaussian(seed_e, (size_t)p.ndig * n, e);
   for (int j = 0; j < p.ndig; ++j) {
@@ -580,8 +576,8 @@ int orc_keygen(int dnum, int log_n, int ell, int h, uint64_t seed_s, uint64_t se
       uint64_t* s2h = (uint64_t*)malloc(n * sizeof(uint64_t));
       uint64_t* eh = (uint64_t*)malloc(n * sizeof(uint64_t));
       for (size_t x = 0; x < n; ++x) {
-        sh[x] = signed_mod(s_out[x], m);
-        s2h[x] = signed_mod(s2_out[x], m);
+        sh[x] = signed_mod(s_from[x], m);
+        s2h[x] = signed_mod(s_to[x], m);
         eh[x] = signed_mod(e[(size_t)j * n + x], m);
       }
       ntt_limb(m, p.psi[t], p.log_n, sh);
@@ -602,7 +598,137 @@ int orc_keygen(int dnum, int log_n, int ell, int h, uint64_t seed_s, uint64_t se
     }
   }
   free(e);
+}
+
+/* The key from s to s2 for two fresh ternary secrets with h nonzeros each
+ * (seeds seed_s, seed_s2); s_out and s2_out receive them. */
+int orc_keygen(int dnum, int log_n, int ell, int h, uint64_t seed_s, uint64_t seed_s2, uint64_t seed_a,
+               uint64_t seed_e, int noiseless, int8_t* s_out, int8_t* s2_out, uint64_t* evk) {
+  orc_params p;
+  if (derive(dnum, log_n, ell, &p) != 0) return -1;
+  size_t n = p.n;
+  if (h < 0 || (size_t)h > n) return -1;
+  ternary(seed_s, n, h, s_out);
+  ternary(seed_s2, n, h, s2_out);
+  int64_t* a = (int64_t*)malloc(n * sizeof(int64_t));
+  int64_t* b = (int64_t*)malloc(n * sizeof(int64_t));
+  for (size_t x = 0; x < n; ++x) { a[x] = s_out[x]; b[x] = s2_out[x]; }
+  make_key(&p, a, b, seed_a, seed_e, noiseless, evk);
+  free(a);
+  free(b);
   return 0;
+}
+
+/* The key from an arbitrary s_from (for instance s*s for relinearisation,
+ * or an automorphism of s for rotation) to s_to. */
+int orc_keygen_pair(int dnum, int log_n, int ell, const int64_t* s_from, const int64_t* s_to, uint64_t seed_a,
+                    uint64_t seed_e, int noiseless, uint64_t* evk) {
+  orc_params p;
+  if (derive(dnum, log_n, ell, &p) != 0) return -1;
+  make_key(&p, s_from, s_to, seed_a, seed_e, noiseless, evk);
+  return 0;
+}
+
+/* ------------------------------------------------- HMUL and HROT (test side) */
+
+/* The Galois automorphism a(X) -> a(X^g) (g odd) of `count` limbs in NTT form,
+ * computed in the coefficient domain: coefficient i moves to i*g mod 2N,
+ * negated when that lands in [N, 2N) (X^N = -1). */
+void orc_automorph(uint64_t q, uint64_t psi, int log_n, const uint64_t* a, uint64_t g, uint64_t* out, int count) {
+  size_t n = (size_t)1 << log_n;
+#pragma omp parallel for schedule(static)
+  for (int c = 0; c < count; ++c) {
+    uint64_t* x = (uint64_t*)malloc(n * sizeof(uint64_t));
+    memcpy(x, a + (size_t)c * n, n * sizeof(uint64_t));
+    intt_limb(q, psi, log_n, x);
+    uint64_t* y = out + (size_t)c * n;
+    for (size_t i = 0; i < n; ++i) {
+      uint64_t e = (uint64_t)(((u128)i * g) % (2 * n));
+      if (e < n) y[e] = x[i];
+      else y[e - n] = x[i] ? q - x[i] : 0;
+    }
+    free(x);
+    ntt_limb(q, psi, log_n, y);
+  }
+}
+
+/* HMUL (Background section): for ciphertexts a = (a0, a1), b = (b0, b1) over
+ * the level's Q (NTT form), out = (a0*b0, a0*b1 + a1*b0) + KS(a1*b1), the
+ * KeySwitch with the top-level key (from s*s to s).
+ * a, b, out [batch][2][level][N]. */
+int orc_hmul_level(int dnum, int log_n, int ell, int level, const uint64_t* a, const uint64_t* b,
+                   const uint64_t* evk, uint64_t* out, int batch) {
+  orc_params p;
+  if (derive_level(dnum, log_n, ell, level, &p) != 0) return -1;
+  size_t n = p.n, L = (size_t)p.ell;
+  uint64_t* d2 = (uint64_t*)malloc((size_t)batch * L * n * sizeof(uint64_t));
+  uint64_t* ks = (uint64_t*)malloc((size_t)batch * 2 * L * n * sizeof(uint64_t));
+  if (!d2 || !ks) { free(d2); free(ks); return -2; }
+  for (int bt = 0; bt < batch; ++bt)
+    for (size_t i = 0; i < L; ++i) {
+      uint64_t q = p.mod[i];
+      const uint64_t* a0 = a + ((size_t)bt * 2 * L + i) * n;
+      const uint64_t* a1 = a + ((size_t)bt * 2 * L + L + i) * n;
+      const uint64_t* b0 = b + ((size_t)bt * 2 * L + i) * n;
+      const uint64_t* b1 = b + ((size_t)bt * 2 * L + L + i) * n;
+      uint64_t* o0 = out + ((size_t)bt * 2 * L + i) * n;
+      uint64_t* o1 = out + ((size_t)bt * 2 * L + L + i) * n;
+      for (size_t x = 0; x < n; ++x) {
+        o0[x] = mulmod(a0[x], b0[x], q);
+        o1[x] = addmod(mulmod(a0[x], b1[x], q), mulmod(a1[x], b0[x], q), q);
+        d2[((size_t)bt * L + i) * n + x] = mulmod(a1[x], b1[x], q);
+      }
+    }
+  int rc = orc_keyswitch_level(dnum, log_n, ell, level, d2, evk, ks, batch);
+  if (rc == 0)
+    for (int bt = 0; bt < batch; ++bt)
+      for (size_t c = 0; c < 2; ++c)
+        for (size_t i = 0; i < L; ++i) {
+          uint64_t q = p.mod[i];
+          uint64_t* o = out + (((size_t)bt * 2 + c) * L + i) * n;
+          const uint64_t* k = ks + (((size_t)bt * 2 + c) * L + i) * n;
+          for (size_t x = 0; x < n; ++x) o[x] = addmod(o[x], k[x], q);
+        }
+  free(d2);
+  free(ks);
+  return rc;
+}
+
+/* HROT by the automorphism X -> X^g: out = (sigma(c0), 0) + KS(sigma(c1)),
+ * the KeySwitch with the top-level key from sigma(s) to s.
+ * ct, out [batch][2][level][N]. */
+int orc_hrot_level(int dnum, int log_n, int ell, int level, const uint64_t* ct, uint64_t g, const uint64_t* evk,
+                   uint64_t* out, int batch) {
+  orc_params p;
+  if (derive_level(dnum, log_n, ell, level, &p) != 0 || (g & 1) == 0) return -1;
+  size_t n = p.n, L = (size_t)p.ell;
+  uint64_t* d = (uint64_t*)malloc((size_t)batch * L * n * sizeof(uint64_t));
+  uint64_t* ks = (uint64_t*)malloc((size_t)batch * 2 * L * n * sizeof(uint64_t));
+  if (!d || !ks) { free(d); free(ks); return -2; }
+  for (int bt = 0; bt < batch; ++bt)
+    for (size_t i = 0; i < L; ++i) {
+      orc_automorph(p.mod[i], p.psi[i], p.log_n, ct + ((size_t)bt * 2 * L + i) * n, g,
+                    out + ((size_t)bt * 2 * L + i) * n, 1);
+      orc_automorph(p.mod[i], p.psi[i], p.log_n, ct + ((size_t)bt * 2 * L + L + i) * n, g,
+                    d + ((size_t)bt * L + i) * n, 1);
+    }
+  int rc = orc_keyswitch_level(dnum, log_n, ell, level, d, evk, ks, batch);
+  if (rc == 0)
+    for (int bt = 0; bt < batch; ++bt)
+      for (size_t i = 0; i < L; ++i) {
+        uint64_t q = p.mod[i];
+        uint64_t* o0 = out + ((size_t)bt * 2 * L + i) * n;
+        uint64_t* o1 = out + ((size_t)bt * 2 * L + L + i) * n;
+        const uint64_t* k0 = ks + ((size_t)bt * 2 * L + i) * n;
+        const uint64_t* k1 = ks + ((size_t)bt * 2 * L + L + i) * n;
+        for (size_t x = 0; x < n; ++x) {
+          o0[x] = addmod(o0[x], k0[x], q);
+          o1[x] = k1[x];
+        }
+      }
+  free(d);
+  free(ks);
+  return rc;
 }
 
 /* Decryption check of a KeySwitch output (test side): per limb q_i,

@@ -245,3 +245,64 @@ def keygen(P: TinyParams, h: int, seeds=(1, 2, 3, 4), noiseless: bool = False):
             aj.append(a)
         evk.append([bj, aj])
     return s, s2, evk
+
+
+def keygen_pair(P: TinyParams, s_from, s_to, seeds=(3, 4), noiseless: bool = False):
+    """The key from s_from to s_to (integer coefficient lists), as keygen."""
+    e = [0] * (P.ndig * P.n) if noiseless else gaussian(seeds[1], P.ndig * P.n)
+    Pbig = math.prod(P.p)
+    evk = []
+    for j in range(P.ndig):
+        dig = P.digit(j)
+        bj, aj = [], []
+        for t in range(P.nl):
+            m = P.moduli[t]
+            sh = ntt_def([v % m for v in s_from], m, P.psi[t], P.log_n)
+            s2h = ntt_def([v % m for v in s_to], m, P.psi[t], P.log_n)
+            eh = ntt_def([v % m for v in e[j * P.n:(j + 1) * P.n]], m, P.psi[t], P.log_n)
+            a = [int(v) % m for v in splitmix64(seeds[0], (j * P.nl + t) * P.n, P.n)]
+            own = Pbig % m if t in dig else 0
+            bj.append([(-a[x] * s2h[x] + eh[x] + own * sh[x]) % m for x in range(P.n)])
+            aj.append(a)
+        evk.append([bj, aj])
+    return evk
+
+
+def automorph_poly(a, g: int):
+    """a(x) -> a(x^g) in Z[x]/(x^N + 1) on a coefficient list."""
+    n = len(a)
+    out = [0] * n
+    for i, v in enumerate(a):
+        e = i * g % (2 * n)
+        if e < n:
+            out[e] += v
+        else:
+            out[e - n] -= v
+    return out
+
+
+def hmul(P: TinyParams, a, b, evk):
+    """a = (a0, a1), b = (b0, b1) NTT-form lists over Q:
+    (a0 b0, a0 b1 + a1 b0) + KS(a1 b1)."""
+    n = P.n
+    d0 = [[a[0][i][x] * b[0][i][x] % P.q[i] for x in range(n)] for i in range(P.ell)]
+    d1 = [[(a[0][i][x] * b[1][i][x] + a[1][i][x] * b[0][i][x]) % P.q[i] for x in range(n)] for i in range(P.ell)]
+    d2 = [[a[1][i][x] * b[1][i][x] % P.q[i] for x in range(n)] for i in range(P.ell)]
+    ks = keyswitch(P, d2, evk)
+    return [[[(d[i][x] + ks[c][i][x]) % P.q[i] for x in range(n)] for i in range(P.ell)]
+            for c, d in enumerate((d0, d1))]
+
+
+def hrot(P: TinyParams, ct, g: int, evk):
+    """(sigma_g(c0), 0) + KS(sigma_g(c1)), sigma_g computed on coefficients."""
+    def sigma(rows):
+        out = []
+        for i in range(P.ell):
+            q = P.q[i]
+            coeffs = intt_def(rows[i], q, P.psi[i], P.log_n)
+            out.append(ntt_def([v % q for v in automorph_poly(coeffs, g)], q, P.psi[i], P.log_n))
+        return out
+    c0, c1 = sigma(ct[0]), sigma(ct[1])
+    ks = keyswitch(P, c1, evk)
+    return [[[(c0[i][x] + ks[0][i][x]) % P.q[i] for x in range(P.n)] for i in range(P.ell)], ks[1]]
+

@@ -66,6 +66,9 @@ _lib.ks_modup.argtypes = [_vp, _vp, _vp, _i, _vp, _vp]
 _lib.ks_keymult.argtypes = [_vp, _vp, _vp, _vp, _i, _vp]
 _lib.ks_moddown.argtypes = [_vp, _vp, _vp, _i, _vp, _vp]
 _lib.ks_keyswitch.argtypes = [_vp, _vp, _vp, _vp, _i, ctypes.POINTER(Plan), _vp, _vp]
+_lib.ks_hmul.argtypes = [_vp, _vp, _vp, _vp, _vp, _i, ctypes.POINTER(Plan), _vp, _vp]
+_lib.ks_hrot.argtypes = [_vp, _vp, _i, _vp, _vp, _i, ctypes.POINTER(Plan), _vp, _vp]
+_lib.ks_eval_workspace_bytes.argtypes = [_vp, _i, ctypes.POINTER(Plan), ctypes.POINTER(_sz)]
 _lib.ks_launch_count.argtypes = [_vp, _i, ctypes.POINTER(Plan)]
 _lib.ks_strerror.argtypes = [_i]
 _lib.ks_strerror.restype = ctypes.c_char_p
@@ -80,9 +83,10 @@ _lib.ks_graph_destroy.argtypes = [_vp]
 _lib.ks_graph_destroy.restype = None
 
 KIND_NAMES = ["intt_d_blocks", "modup_cols", "keymult_blocks", "moddown_cols", "moddown_blocks", "ext_blocks",
-              "pblocks_inv", "copy_digits", "keymult", "bconv", "ntt"]
+              "pblocks_inv", "copy_digits", "keymult", "bconv", "ntt", "eval"]
 
-EXPORTED = ["ks_params_create", "ks_params_destroy", "ks_params_at_level", "ks_params_info", "ks_workspace_bytes", "ks_default_plan",
+EXPORTED = ["ks_params_create", "ks_params_destroy", "ks_params_at_level", "ks_params_info", "ks_workspace_bytes",
+            "ks_default_plan", "ks_hmul", "ks_hrot", "ks_eval_workspace_bytes",
             "ks_ntt", "ks_intt", "ks_bconv", "ks_modup", "ks_keymult", "ks_moddown", "ks_keyswitch",
             "ks_launch_count", "ks_strerror", "ks_last_hip_error", "ks_trace_begin", "ks_trace_end",
             "ks_graph_create", "ks_graph_launch", "ks_graph_destroy"]
@@ -209,6 +213,26 @@ class KsParams:
     def keyswitch(self, d, evk, out, batch, ws, plan: Plan = None, stream=None):
         _check(_lib.ks_keyswitch(self._h, _ptr(d), _ptr(evk), _ptr(out), batch,
                                  ctypes.byref(plan) if plan else None, _ptr(ws), _stream(stream)), "ks_keyswitch")
+
+    def eval_workspace_bytes(self, batch: int, plan: Plan = None) -> int:
+        b = _sz()
+        _check(_lib.ks_eval_workspace_bytes(self._h, batch, ctypes.byref(plan) if plan else None, ctypes.byref(b)),
+               "ks_eval_workspace_bytes")
+        return int(b.value)
+
+    def eval_workspace(self, batch: int, plan: Plan = None, device="cuda") -> torch.Tensor:
+        nbytes = max(self.eval_workspace_bytes(batch, plan), 8)
+        return torch.empty((nbytes + 7) // 8, dtype=torch.int64, device=device)
+
+    def hmul(self, a, b, evk, out, batch, ws, plan: Plan = None, stream=None):
+        """(a0 b0, a0 b1 + a1 b0) + KeySwitch(a1 b1); evk from s*s to s."""
+        _check(_lib.ks_hmul(self._h, _ptr(a), _ptr(b), _ptr(evk), _ptr(out), batch,
+                            ctypes.byref(plan) if plan else None, _ptr(ws), _stream(stream)), "ks_hmul")
+
+    def hrot(self, ct, galois, evk, out, batch, ws, plan: Plan = None, stream=None):
+        """(sigma(c0), 0) + KeySwitch(sigma(c1)) for x -> x^galois; evk from sigma(s) to s."""
+        _check(_lib.ks_hrot(self._h, _ptr(ct), galois, _ptr(evk), _ptr(out), batch,
+                            ctypes.byref(plan) if plan else None, _ptr(ws), _stream(stream)), "ks_hrot")
 
     def graph(self, d, evk, out, batch, ws, plan: Plan = None, stream=None) -> "Graph":
         """Capture one KeySwitch on these buffers into a replayable HIP graph."""

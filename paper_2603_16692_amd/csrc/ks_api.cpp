@@ -517,6 +517,78 @@ int ks_keyswitch(const ks_params* p, const uint64_t* d, const uint64_t* evk, uin
   return KS_OK;
 }
 
+// HMUL and HROT: element-wise pre-pass into the workspace, the KeySwitch of
+// one component straight into `out`, then the other part added to `out`.
+// Workspace: [t01: B*2*ell*N][d: B*ell*N][KeySwitch workspace].
+static size_t eval_extra(const ks_params* p, int batch) {
+  return up256((size_t)batch * 3 * p->hp.ell * p->hp.n * sizeof(uint64_t));
+}
+
+int ks_eval_workspace_bytes(const ks_params* p, int batch, const ks_plan* plan, size_t* bytes) {
+  if (!p || !bytes) return KS_ENULL;
+  size_t ks = 0;
+  const int rc = ks_workspace_bytes(p, batch, plan, &ks);
+  if (rc != KS_OK) return rc;
+  *bytes = eval_extra(p, batch) + ks;
+  return KS_OK;
+}
+
+static int eval_check(const ks_params* p, const void* x, const void* y, const uint64_t* evk, const uint64_t* out,
+                      void* ws) {
+  int rc;
+  if ((rc = check_ptr(x)) != KS_OK || (y && (rc = check_ptr(y)) != KS_OK) || (rc = check_ptr(evk)) != KS_OK ||
+      (rc = check_ptr(out)) != KS_OK || (rc = check_ptr(ws)) != KS_OK)
+    return rc;
+  return KS_OK;
+}
+
+int ks_hmul(const ks_params* p, const uint64_t* a, const uint64_t* b, const uint64_t* evk, uint64_t* out, int batch,
+            const ks_plan* plan, void* ws, void* stream) {
+  if (!p) return KS_ENULL;
+  if (batch < 0 || batch * std::max(2, p->hp.ndig) > 65535) return KS_EINVAL;
+  ks_plan pl;
+  int rc = resolve_plan(p, plan, pl);
+  if (rc != KS_OK) return rc;
+  if (batch == 0) return KS_OK;
+  if ((rc = eval_check(p, a, b, evk, out, ws)) != KS_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t LN = (size_t)p->hp.ell * p->hp.n;
+  uint64_t* t01 = reinterpret_cast<uint64_t*>(ws);
+  uint64_t* d2 = t01 + (size_t)batch * 2 * LN;
+  char* ksws = reinterpret_cast<char*>(ws) + eval_extra(p, batch);
+  KS_TRY(traced(KS_K_EVAL, s, [&] { return ks::launch_tensor(p->tb, a, b, t01, d2, batch, s); }));
+  if ((rc = ks_keyswitch(p, d2, evk, out, batch, &pl, ksws, stream)) != KS_OK) return rc;
+  KS_TRY(traced(KS_K_EVAL, s, [&] { return ks::launch_add_q(p->tb, out, t01, 2, batch, s); }));
+  return KS_OK;
+}
+
+int ks_hrot(const ks_params* p, const uint64_t* ct, int galois, const uint64_t* evk, uint64_t* out, int batch,
+            const ks_plan* plan, void* ws, void* stream) {
+  if (!p) return KS_ENULL;
+  if (batch < 0 || batch * std::max(2, p->hp.ndig) > 65535) return KS_EINVAL;
+  if (galois <= 0 || (galois & 1) == 0 || (size_t)galois >= 2 * p->hp.n) return KS_EINVAL;
+  ks_plan pl;
+  int rc = resolve_plan(p, plan, pl);
+  if (rc != KS_OK) return rc;
+  if (batch == 0) return KS_OK;
+  if ((rc = eval_check(p, ct, nullptr, evk, out, ws)) != KS_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t LN = (size_t)p->hp.ell * p->hp.n;
+  uint64_t* t01 = reinterpret_cast<uint64_t*>(ws);  // sigma(c0) in component 0
+  uint64_t* d = t01 + (size_t)batch * 2 * LN;        // sigma(c1)
+  char* ksws = reinterpret_cast<char*>(ws) + eval_extra(p, batch);
+  const int ell = p->hp.ell;
+  KS_TRY(traced(KS_K_EVAL, s, [&] {
+    return ks::launch_automorph(p->tb, ct, t01, ell, 2 * LN, 2 * LN, (uint32_t)galois, batch, s);
+  }));
+  KS_TRY(traced(KS_K_EVAL, s, [&] {
+    return ks::launch_automorph(p->tb, ct + LN, d, ell, 2 * LN, LN, (uint32_t)galois, batch, s);
+  }));
+  if ((rc = ks_keyswitch(p, d, evk, out, batch, &pl, ksws, stream)) != KS_OK) return rc;
+  KS_TRY(traced(KS_K_EVAL, s, [&] { return ks::launch_add_q(p->tb, out, t01, 1, batch, s); }));
+  return KS_OK;
+}
+
 const char* ks_strerror(int code) {
   switch (code) {
     case KS_OK: return "ok";

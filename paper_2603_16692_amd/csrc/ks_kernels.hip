@@ -1008,6 +1008,57 @@ __global__ void k_bconv(DevTables tb, const uint64_t* src, uint64_t* dst, int se
   dst[((size_t)item * nd + u) * N + x] = reduce2(mul_shoup(z, 1, L.red_s, L.q), L.q);
 }
 
+// ------------------------------------------------- HMUL and HROT (element-wise)
+
+// HMUL's tensor product over the Q limbs: for ciphertexts a, b
+// [items][2][ell][N] (canonical, NTT form): t01 [items][2][ell][N] gets
+// (a0 b0, a0 b1 + a1 b0) and d2 [items][ell][N] gets a1 b1, canonical.
+// Grid: (ceil(N / 256), ell, items).
+__global__ __launch_bounds__(256) void k_tensor(DevTables tb, const uint64_t* a, const uint64_t* b, uint64_t* t01,
+                                                uint64_t* d2) {
+  const size_t N = (size_t)1 << tb.log_n;
+  const size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= N) return;
+  const int i = blockIdx.y, item = blockIdx.z, ell = tb.ell;
+  const LimbC L = tb.limb[i];
+  const size_t r0 = (((size_t)item * 2 + 0) * ell + i) * N + x, r1 = (((size_t)item * 2 + 1) * ell + i) * N + x;
+  const double a0 = u2d(a[r0]), a1 = u2d(a[r1]), b0 = u2d(b[r0]), b1 = u2d(b[r1]);
+  t01[r0] = f_canon(f_mul(a0, b0, L.qd, L.qinv), L.qd, L.qinv);
+  t01[r1] = f_canon(f_mul(a0, b1, L.qd, L.qinv) + f_mul(a1, b0, L.qd, L.qinv), L.qd, L.qinv);
+  d2[((size_t)item * ell + i) * N + x] = f_canon(f_mul(a1, b1, L.qd, L.qinv), L.qd, L.qinv);
+}
+
+// The Galois automorphism x -> x^g on NTT-form limbs: slot t holds the value at
+// psi^(2 brv(t) + 1), so slot t of the image is slot t' of the input with
+// 2 brv(t') + 1 = g (2 brv(t) + 1) mod 2N. src and dst [rows][N] (rows =
+// gridDim.y * gridDim.z, any limbs), dst must not alias src.
+// Grid: (ceil(N / 256), rows per item, items).
+__global__ __launch_bounds__(256) void k_automorph(int log_n, const uint64_t* src, uint64_t* dst, uint32_t g,
+                                                   size_t src_item_stride, size_t dst_item_stride) {
+  const uint32_t N = 1u << log_n;
+  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= N) return;
+  const uint32_t e = 2u * (__brev(t) >> (32 - log_n)) + 1u;
+  const uint32_t e2 = (uint32_t)(((uint64_t)g * e) & (2u * N - 1u));
+  const uint32_t t2 = __brev((e2 - 1u) >> 1) >> (32 - log_n);
+  const size_t row = blockIdx.y;
+  dst[(size_t)blockIdx.z * dst_item_stride + row * N + t] = src[(size_t)blockIdx.z * src_item_stride + row * N + t2];
+}
+
+// out[item][c][i] += add[item][c][i] mod q_i for c < ncomp (both canonical).
+// Grid: (ceil(N / 256), ncomp * ell, items).
+__global__ __launch_bounds__(256) void k_add_q(DevTables tb, uint64_t* out, const uint64_t* add) {
+  const size_t N = (size_t)1 << tb.log_n;
+  const size_t x = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= N) return;
+  const int ell = tb.ell;
+  const int c = blockIdx.y / ell, i = blockIdx.y % ell, item = blockIdx.z;
+  const uint64_t q = tb.limb[i].q;
+  const size_t r = (((size_t)item * 2 + c) * ell + i) * N + x;
+  const uint64_t v = out[r] + add[r];
+  out[r] = v >= q ? v - q : v;
+}
+
 // ks_keymult: element-wise over acc [items][2][nl][N], integer arithmetic.
 __global__ void k_keymult(DevTables tb, const uint64_t* ext, const uint64_t* evk, uint64_t* acc) {
   const size_t N = (size_t)1 << tb.log_n;
@@ -1397,6 +1448,28 @@ hipError_t launch_bconv(const DevTables& tb, const uint64_t* src, int set, uint6
     nd = tb.nl - (hi - lo);
   }
   k_bconv<<<dim3((n + 255) / 256, nd, items), dim3(256), 0, s>>>(tb, src, dst, set);
+  return hipGetLastError();
+}
+
+hipError_t launch_tensor(const DevTables& tb, const uint64_t* a, const uint64_t* b, uint64_t* t01, uint64_t* d2,
+                         int items, hipStream_t s) {
+  const unsigned n = 1u << tb.log_n;
+  k_tensor<<<dim3((n + 255) / 256, tb.ell, items), dim3(256), 0, s>>>(tb, a, b, t01, d2);
+  return hipGetLastError();
+}
+
+hipError_t launch_automorph(const DevTables& tb, const uint64_t* src, uint64_t* dst, int rows, size_t src_item_stride,
+                            size_t dst_item_stride, uint32_t g, int items, hipStream_t s) {
+  const unsigned n = 1u << tb.log_n;
+  k_automorph<<<dim3((n + 255) / 256, rows, items), dim3(256), 0, s>>>(tb.log_n, src, dst, g, src_item_stride,
+                                                                       dst_item_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_q(const DevTables& tb, uint64_t* out, const uint64_t* add, int ncomp, int items,
+                        hipStream_t s) {
+  const unsigned n = 1u << tb.log_n;
+  k_add_q<<<dim3((n + 255) / 256, ncomp * tb.ell, items), dim3(256), 0, s>>>(tb, out, add);
   return hipGetLastError();
 }
 

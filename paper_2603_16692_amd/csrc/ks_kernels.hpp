@@ -44,6 +44,15 @@ hipError_t launch_pblocks_inv(const DevTables& tb, int log_r, const uint64_t* ac
                               hipStream_t s);
 hipError_t launch_copy_digits(const DevTables& tb, const uint64_t* d, uint64_t* ext, int items, hipStream_t s);
 hipError_t launch_bconv(const DevTables& tb, const uint64_t* src, int set, uint64_t* dst, int items, hipStream_t s);
+// HMUL tensor product: t01 [items][2][ell][N] = (a0 b0, a0 b1 + a1 b0), d2 [items][ell][N] = a1 b1.
+hipError_t launch_tensor(const DevTables& tb, const uint64_t* a, const uint64_t* b, uint64_t* t01, uint64_t* d2,
+                         int items, hipStream_t s);
+// Galois automorphism x -> x^g of `rows` NTT-form limbs per item (strides in words).
+hipError_t launch_automorph(const DevTables& tb, const uint64_t* src, uint64_t* dst, int rows, size_t src_item_stride,
+                            size_t dst_item_stride, uint32_t g, int items, hipStream_t s);
+// out [items][2][ell][N] += add (same layout) for components c < ncomp, mod q_i.
+hipError_t launch_add_q(const DevTables& tb, uint64_t* out, const uint64_t* add, int ncomp, int items,
+                        hipStream_t s);
 hipError_t launch_keymult(const DevTables& tb, const uint64_t* ext, const uint64_t* evk, uint64_t* acc, int items,
                           hipStream_t s);
 

@@ -92,3 +92,62 @@ def decrypt_ok(P, d, out, s, s2, h, batch):
     agree, err = oracle.ks_error(P, d, out, s, s2, batch)
     m = int(np.abs(err).max())
     return agree and m <= oracle.ks_bound(P, h), m
+
+
+def _limb_decrypt(P, lhs_rows, rhs_rows):
+    """(agree, max|e|) of e = INTT(lhs - rhs) over the limbs of P, as centered integers."""
+    err = None
+    agree = True
+    for i, q in enumerate(P.q):
+        diff = (lhs_rows[i].astype(object) - rhs_rows[i].astype(object)) % q
+        e = oracle.intt(q, P.psi[i], P.log_n, np.array(diff, dtype=np.uint64))
+        c = np.array([int(v) - q if int(v) > q // 2 else int(v) for v in e], dtype=np.int64)
+        if err is None:
+            err = c
+        elif not np.array_equal(err, c):
+            agree = False
+    return agree, int(np.abs(err).max())
+
+
+def _ntt_secret(P, s, i):
+    q = P.q[i]
+    return oracle.ntt(q, P.psi[i], P.log_n, np.array([int(v) % q for v in s], dtype=np.uint64)).astype(object)
+
+
+def hmul_decrypt_ok(P, a, b, out, s, h, batch):
+    """out0 + out1*s must equal (a0 + a1 s)(b0 + b1 s) up to a KeySwitch error
+    within the noise bound, at every limb the same integer."""
+    worst, ok = 0, True
+    for bt in range(batch):
+        lhs, rhs = [], []
+        for i, q in enumerate(P.q):
+            sh = _ntt_secret(P, s, i)
+            a0, a1 = a[bt, 0, i].astype(object), a[bt, 1, i].astype(object)
+            b0, b1 = b[bt, 0, i].astype(object), b[bt, 1, i].astype(object)
+            lhs.append((out[bt, 0, i].astype(object) + out[bt, 1, i].astype(object) * sh) % q)
+            rhs.append((a0 + a1 * sh) * (b0 + b1 * sh) % q)
+        agree, m = _limb_decrypt(P, lhs, rhs)
+        ok = ok and agree
+        worst = max(worst, m)
+    return ok and worst <= oracle.ks_bound(P, h), worst
+
+
+def hrot_decrypt_ok(P, ct, g, out, s, h, batch):
+    """out0 + out1*s must equal sigma_g(c0) + sigma_g(c1)*sigma_g(s) (the
+    rotated ciphertext under the rotated secret), up to a KeySwitch error
+    within the noise bound; sigma_g(s) is taken on the coefficients of s."""
+    gs = oracle.automorph_coeffs(s, g)
+    worst, ok = 0, True
+    for bt in range(batch):
+        lhs, rhs = [], []
+        for i, q in enumerate(P.q):
+            sh = _ntt_secret(P, s, i)
+            gsh = _ntt_secret(P, gs, i)
+            c0 = oracle.automorph(q, P.psi[i], P.log_n, ct[bt, 0, i], g).astype(object)
+            c1 = oracle.automorph(q, P.psi[i], P.log_n, ct[bt, 1, i], g).astype(object)
+            lhs.append((out[bt, 0, i].astype(object) + out[bt, 1, i].astype(object) * sh) % q)
+            rhs.append((c0 + c1 * gsh) % q)
+        agree, m = _limb_decrypt(P, lhs, rhs)
+        ok = ok and agree
+        worst = max(worst, m)
+    return ok and worst <= oracle.ks_bound(P, h), worst

@@ -1,0 +1,92 @@
+"""Bit-exact parity of ks_hmul and ks_hrot (the ciphertext product with
+relinearisation, and the slot rotation) against the oracle, at the top level
+and at lower levels, under several KeySwitch plans, and by decryption at a
+benchmark size."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import ciphertext_batch
+
+import pins
+from gpu_util import dev, empty, first_mismatch, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ks():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2603_16692_amd as k
+    return k
+
+
+def _ct(P, batch, seed):
+    return ciphertext_batch(P.q, P.n, 2 * batch, seed_base=seed).reshape(batch, 2, P.ell, P.n)
+
+
+def assert_same(gpu, ref, what):
+    mm = first_mismatch(gpu, ref)
+    assert mm is None, f"{what}: first mismatch {mm}"
+
+
+@pytest.mark.parametrize("dnum,log_n,ell,levels", [(3, 12, 7, [7, 3]), (2, 10, 5, [5, 1]), (4, 13, 16, [16, 9])])
+def test_hmul_and_hrot_match_oracle(ks, dnum, log_n, ell, levels):
+    top = ks.KsParams(dnum, log_n, ell)
+    Pt = oracle.Params(dnum, log_n, ell)
+    s, _, _ = oracle.keygen(Pt, h=64)
+    mk = dev(oracle.keygen_pair(Pt, oracle.negacyclic_product(s, s), s))
+    batch = 3
+    for level in levels:
+        G = top.at_level(level) if level != ell else top
+        P = Pt.at_level(level)
+        a, b = _ct(P, batch, 10 + level), _ct(P, batch, 20 + level)
+        ref = oracle.hmul(P, a, b, host(mk).reshape(P.key_shape), batch)
+        for plan in (None, ks.make_plan(ks.DPOB, 1, 2, mfma=True), ks.make_plan(ks.DSOC, min(2, level), 3),
+                     ks.make_plan(ks.STAGED)):
+            out = empty(ref.shape)
+            G.hmul(dev(a), dev(b), mk, out, batch, G.eval_workspace(batch, plan), plan)
+            assert_same(host(out), ref, f"hmul level {level} {plan}")
+        for g in (5, 25, 2 * P.n - 1):
+            rk_h = oracle.keygen_pair(Pt, oracle.automorph_coeffs(s, g), s)
+            ref = oracle.hrot(P, a, g, rk_h, batch)
+            out = empty(ref.shape)
+            plan = ks.make_plan(ks.DPOB, 1, 2, mfma=True)
+            G.hrot(dev(a), g, dev(rk_h), out, batch, G.eval_workspace(batch, plan), plan)
+            assert_same(host(out), ref, f"hrot g={g} level {level}")
+
+
+def test_hrot_rejects_bad_galois_elements(ks):
+    G = ks.KsParams(2, 10, 5)
+    ct = empty((1, 2, 5, 1 << 10))
+    out = empty((1, 2, 5, 1 << 10))
+    evk = empty(G.shapes(1)["evk"])
+    ws = G.eval_workspace(1)
+    for g in (0, 4, 2048, 2049, -3):
+        with pytest.raises(ks.KsError) as e:
+            G.hrot(ct, g, evk, out, 1, ws)
+        assert e.value.code == ks.KS_EINVAL
+
+
+def test_hmul_hrot_decrypt_at_benchmark_size(ks):
+    dnum, log_n, ell, batch = 2, 15, 10, 2
+    G = ks.KsParams(dnum, log_n, ell)
+    P = oracle.Params(dnum, log_n, ell)
+    s, _, _ = oracle.keygen(P, h=64)
+    mk = oracle.keygen_pair(P, oracle.negacyclic_product(s, s), s)
+    a, b = _ct(P, batch, 31), _ct(P, batch, 32)
+    plan = ks.make_plan(ks.DPOB, 1, 3, mfma=True)
+    out = empty((batch, 2, ell, P.n))
+    G.hmul(dev(a), dev(b), dev(mk), out, batch, G.eval_workspace(batch, plan), plan)
+    got = host(out)
+    assert_same(got, oracle.hmul(P, a, b, mk, batch), "hmul")
+    ok, m = pins.hmul_decrypt_ok(P, a, b, got, s, 64, batch)
+    assert ok, m
+    g = 5 ** 3 % (2 * P.n)
+    rk = oracle.keygen_pair(P, oracle.automorph_coeffs(s, g), s)
+    G.hrot(dev(a), g, dev(rk), out, batch, G.eval_workspace(batch, plan), plan)
+    got = host(out)
+    assert_same(got, oracle.hrot(P, a, g, rk, batch), "hrot")
+    ok, m = pins.hrot_decrypt_ok(P, a, g, got, s, 64, batch)
+    assert ok, m
