@@ -93,6 +93,27 @@ def kernel_bytes(G, plan, batch, kind):
     return None
 
 
+# FP64 modular products per second at the chip's vector rate: 256 CUs x 4 SIMDs
+# x 16 lanes x 2.4 GHz = 39.3 T lane-operations/s, 6 FP64 operations per
+# product (h = ab, l = fma(a, b, -h), h/q, rint, fma(-k, q, h), + l).
+MODMUL_PEAK_T = 256 * 4 * 16 * 2.4e9 / 6 / 1e12
+
+
+def kernel_modmuls(G, plan, batch, kind):
+    """Algorithmic modular products of all launches of `kind` in one step (Q
+    limbs, FP64): butterflies of its block passes (log M stages of N/2), key
+    products and the final P^-1, or None for kinds not modelled."""
+    import paper_2603_16692_amd as ks
+    N, B, ell, nd = G.n, batch, G.ell, G.ndig
+    log_m = G.log_n - plan.log_r
+    if kind != 4:
+        return None
+    if plan.dataflow in (ks.DPOB, ks.DPOC):
+        # per Q limb: both t2 components and the raised limb of every other digit
+        return B * ell * ((nd + 1) * log_m * N // 2 + 2 * nd * N + 2 * N)
+    return B * 2 * ell * (log_m * N // 2 + N)
+
+
 def percentile(xs, p):
     xs = sorted(xs)
     if not xs:
@@ -301,6 +322,17 @@ def main():
                     "traffic": measured_traffic(args.workload, repr(plan), ks.KIND_NAMES[dominant]),
                     "kernel": ks.KIND_NAMES[dominant], "kernel_avg_ms": round(dom_avg_ms, 4),
                     "launches_per_step": per_step, "algorithmic_bytes_per_launch": int(per_launch)}
+        if roofline["traffic"]:
+            # bytes that left L2 (MALL hits included) and came back, per second of the kernel
+            roofline["measured_GBs"] = round(roofline["traffic"] / (dom_avg_ms / 1e3) / 1e9, 1)
+
+    roofline_alu = None
+    nmm = kernel_modmuls(G, plan, batch, dominant) if args.op == "keyswitch" else None
+    if nmm is not None:
+        rate = nmm / per_step / (dom_avg_ms / 1e3) / 1e12
+        roofline_alu = {"bound": "alu", "achieved": round(rate, 3), "peak": round(MODMUL_PEAK_T, 3),
+                        "unit": "T modmul/s", "frac": round(rate / MODMUL_PEAK_T, 4), "kernel": ks.KIND_NAMES[dominant],
+                        "modmuls_per_launch": int(nmm / per_step)}
 
     # algorithmic bytes of the whole KeySwitch: d + out + evk / batch
     ks_bytes = (lv * G.n * 8) + (2 * lv * G.n * 8) + (2 * G.ndig * G.nl * G.n * 8) / batch
@@ -338,6 +370,7 @@ def main():
         "breakdown_ms": {ks.KIND_NAMES[k]: round(v, 4) for k, v in sorted(per_kind.items())},
         "wall_s": round(t1 - t0, 4),
         "roofline": roofline,
+        "roofline_alu": roofline_alu,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

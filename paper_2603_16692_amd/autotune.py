@@ -207,3 +207,58 @@ def plan_for(params, batch: int, cache: dict):
 
 def describe(plan) -> str:
     return repr(plan)
+
+
+# The paper's parameter grid (Evaluation section): N in 2^14..2^17,
+# L in {10, 30, 50}, dnum in {2, 4, 6, 8}.
+PAPER_GRID = {"log_n": (14, 15, 16, 17), "ell": (10, 30, 50), "dnum": (2, 4, 6, 8)}
+
+
+def grid_map(batch: int = 1, chunk_range=(2, 4, 8), reps: int = 3, trials: int = 2, table: dict = None,
+             grid=PAPER_GRID, log=print):
+    """Tune every (dnum, N, L) of the grid on the current device (the
+    per-parameter dataflow map of the paper's Fig. 4, measured here). Returns
+    one row per set: the winning plan, its time, and the best time of each
+    dataflow over the other knobs (NTT split, chunks, BConv variant, split)."""
+    import numpy as np
+
+    from . import KsParams
+    from synth import ciphertext_batch, uniform_key
+
+    rows = []
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda")
+    for log_n in grid["log_n"]:
+        for ell in grid["ell"]:
+            for dnum in grid["dnum"]:
+                G = KsParams(dnum, log_n, ell)
+                d = dev(ciphertext_batch(G.moduli[:ell], G.n, batch))
+                evk = dev(uniform_key(G.moduli, G.n, G.ndig))
+                plans = prior_order(G, batch, candidate_plans(G, batch, chunk_range))
+                best, results = tune(G, d, evk, batch, plans=plans, reps=reps, trials=trials, cache=table)
+                per_df = {}
+                for r in results:
+                    name = DATAFLOW_NAMES[r["plan"][0]]
+                    if r["bit_exact"] and (name not in per_df or r["ms"] < per_df[name]):
+                        per_df[name] = r["ms"]
+                row = {"dnum": dnum, "log_n": log_n, "L": ell, "batch": batch, "best": repr(best),
+                       "best_ms": min(per_df.values()), "per_dataflow_ms": per_df, "plans": len(results),
+                       "footprint_dpob_mb": footprint_bytes(dnum, G.n, ell, DPOB, 1, batch) / 1e6}
+                rows.append(row)
+                log(json.dumps(row))
+                del G, d, evk
+                torch.cuda.empty_cache()
+    return rows
+
+
+if __name__ == "__main__":
+    import argparse
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    ap = argparse.ArgumentParser(description="per-parameter dataflow map over the paper's grid")
+    ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--save-tuned", default="", help="merge the winners into this JSON table")
+    args = ap.parse_args()
+    table = load_cache(args.save_tuned) if args.save_tuned else {}
+    grid_map(args.batch, table=table, log=lambda s: print(s, flush=True))
+    if args.save_tuned:
+        save_cache(table, args.save_tuned)

@@ -90,7 +90,22 @@ int resolve_plan(const ks_params* p, const ks_plan* in, ks_plan& out) {
   }
   if (out.flags & ~(KS_PLAN_MFMA_BCONV | KS_PLAN_SPLIT_STREAMS)) return KS_EUNSUP;
   if (out.dataflow < KS_DSOB || out.dataflow > KS_STAGED) return KS_EUNSUP;
-  if (out.log_r < 0) out.log_r = default_log_r(p->hp.log_n);
+  if (out.log_r < 0) {
+    // the default split, or the nearest smaller one whose column kernels can
+    // stage the digit's and P's limbs (large alpha), or a larger one if the
+    // blocks would otherwise exceed 2^14 coefficients
+    const int d = default_log_r(p->hp.log_n);
+    auto fits = [&](int r) {
+      const int m = p->hp.log_n - r;
+      return m >= 3 && m <= 14 && ks::stage_cap(p->hp.alpha, r) && ks::stage_cap(p->hp.k, r);
+    };
+    out.log_r = d;
+    for (int r = d; r >= 0; --r)
+      if (fits(r)) { out.log_r = r; break; }
+    if (!fits(out.log_r))
+      for (int r = d + 1; r <= 5; ++r)
+        if (fits(r)) { out.log_r = r; break; }
+  }
   const int log_m = p->hp.log_n - out.log_r;
   if (out.log_r > 5 || log_m < 3 || log_m > 14) return KS_EUNSUP;
   if (ks::stage_cap(p->hp.alpha, out.log_r) == 0 || ks::stage_cap(p->hp.k, out.log_r) == 0) return KS_EUNSUP;

@@ -297,3 +297,17 @@ def test_launch_counts_follow_table_iii(ks):
     assert G.launch_count(4, sp) == 2 * G.launch_count(4, ks.make_plan(ks.DPOB))
     assert G.launch_count(1, sp) == G.launch_count(1, ks.make_plan(ks.DPOB))
     assert G.workspace_bytes(5, sp) == G.workspace_bytes(2) + G.workspace_bytes(3)
+
+
+def test_default_plan_valid_for_large_digits(ks):
+    # alpha = 25: the default NTT split is reduced until the column kernels can stage the digit
+    for dnum, log_n, ell in ((2, 16, 50), (2, 17, 50), (1, 12, 30)):
+        G = ks.KsParams(dnum, log_n, ell)
+        p = G.default_plan(1)
+        assert G.workspace_bytes(1, p) > 0 and p.log_r >= 0
+    G, P = params(ks, 1, 12, 30)
+    d = ciphertext_batch(P.q, P.n, 1)
+    _, _, evk = oracle.keygen(P, h=64)
+    out = empty((1, 2, P.ell, P.n))
+    G.keyswitch(dev(d), dev(evk), out, 1, G.workspace(1))
+    assert_same(host(out), oracle.keyswitch(P, d, evk, 1), "alpha = 30")
