@@ -176,8 +176,10 @@ int ks_keyswitch(const ks_params* p, const uint64_t* d, const uint64_t* evk, uin
  * canonical NTT form over the handle's Q (or level),
  *   out = (a0*b0, a0*b1 + a1*b0) + KeySwitch(a1*b1),
  * with evk the key from s*s to s (top-level layout, as ks_keyswitch). The
- * KeySwitch runs under `plan` (NULL = default). ws: ks_eval_workspace_bytes
- * bytes. out must not alias a or b. Asynchronous on `stream`. */
+ * KeySwitch runs under `plan` (NULL = default); a fused plan computes a1*b1
+ * in its first pass and adds the other terms in its last, KS_STAGED runs
+ * them as kernels of their own. ws: ks_eval_workspace_bytes bytes. out must
+ * not alias a or b. Asynchronous on `stream`. */
 int ks_hmul(const ks_params* p, const uint64_t* a, const uint64_t* b, const uint64_t* evk, uint64_t* out, int batch,
             const ks_plan* plan, void* ws, void* stream);
 

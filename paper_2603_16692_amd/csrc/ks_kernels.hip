@@ -193,6 +193,47 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), LOGM >= 12 ? 4 : 1) void k_bl
   }
 }
 
+// HMUL's first pass: one block b of Q limb i of one item per workgroup
+// (placed by xcd_tile): d2 = a1 * b1 (canonical) into d2 [items][ell][N], and
+// its inverse block pass into t1 [items][ell][N], as k_blocks does for d.
+// a, b [items][2][ell][N] canonical.
+template <int LOGM, int LOGE>
+__global__ __launch_bounds__((1 << (LOGM - LOGE)), LOGM >= 12 ? 4 : 1) void k_tensor_blocks(
+    DevTables tb, const uint64_t* a, const uint64_t* b, uint64_t* d2, uint64_t* t1, int items) {
+  using B = BlockNtt<LOGM, LOGE>;
+  extern __shared__ uint64_t lds[];
+  const size_t N = (size_t)1 << tb.log_n;
+  const int R = (int)(N >> LOGM), ell = tb.ell;
+  const Tile tl = xcd_tile(R * ell, items);
+  if (!tl.valid) return;
+  const int tid = threadIdx.x, blk = tl.tile % R, i = tl.tile / R;
+  const LimbC L = tb.limb[i];
+  const size_t boff = (size_t)blk * B::M;
+  const uint64_t* a1 = a + (((size_t)tl.item * 2 + 1) * ell + i) * N + boff;
+  const uint64_t* b1 = b + (((size_t)tl.item * 2 + 1) * ell + i) * N + boff;
+  const size_t off = ((size_t)tl.item * ell + i) * N + boff;
+  double v[B::E];
+#pragma unroll
+  for (int e = 0; e < B::E; ++e) {
+    const int x = B::cl_pos(tid, e);
+    const uint64_t c = f_canon(f_mul(u2d(a1[x]), u2d(b1[x]), L.qd, L.qinv), L.qd, L.qinv);
+    d2[off + x] = c;
+    v[e] = u2d(c);
+  }
+  B::inv(arf(tb, L, i, true), v, reinterpret_cast<double*>(lds), tid, (uint32_t)(R + blk));
+#pragma unroll
+  for (int e = 0; e < B::E; ++e) t1[off + B::fr_pos(tid, e)] = f_canon(v[e], L.qd, L.qinv);
+}
+
+// HMUL's tensor terms of one element, added to a ModDown output pair:
+// (o0, o1) += (a0 b0, a0 b1 + a1 b0), all reduced; r0 / r1 index component 0 / 1.
+__device__ __forceinline__ void add_tensor(const LimbC& L, const uint64_t* a, const uint64_t* b, size_t r0, size_t r1,
+                                           double& o0, double& o1) {
+  const double a0 = u2d(a[r0]), a1 = u2d(a[r1]), b0 = u2d(b[r0]), b1 = u2d(b[r1]);
+  o0 += f_mul(a0, b0, L.qd, L.qinv);
+  o1 += f_mul(a0, b1, L.qd, L.qinv) + f_mul(a1, b0, L.qd, L.qinv);
+}
+
 // ------------------------------------------------------------ ModUp (K2)
 
 // A column-pass workgroup: 8 waves over the same 64 columns (the 64 lanes).
@@ -768,7 +809,8 @@ __global__ __launch_bounds__(CT, LOGR == 4 ? 4 : 1) void k_moddown_cols_mx(DevTa
 template <int LOGM, int LOGE>
 __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_moddown_blocks(DevTables tb, const uint64_t* t2,
                                                                          const uint64_t* acc, uint64_t* out,
-                                                                         int tgt0, int ntgt, int ics) {
+                                                                         int tgt0, int ntgt, int ics,
+                                                                         const uint64_t* ta, const uint64_t* tb2) {
   using B = BlockNtt<LOGM, LOGE>;
   extern __shared__ uint64_t lds[];
   const size_t N = (size_t)1 << tb.log_n;
@@ -789,11 +831,21 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_moddown_blocks(DevTabl
   const uint64_t* a = acc + ((size_t)ic * tb.nl + i) * N + boff;
   uint64_t* o = out + ((size_t)ic * tb.ell + i) * N + boff;
   const double pinv = tb.dn_pinv_d[i];
+  const int item = ic >> 1, comp = ic & 1;
+  const size_t r0 = ((size_t)item * 2 * tb.ell + i) * N + boff, r1 = r0 + (size_t)tb.ell * N;
 #pragma unroll
   for (int e = 0; e < B::E; ++e) {
     const int x = B::cl_pos(tid, e);
-    // |acc - v| <= 2.4q, |P^-1| <= q/2
-    o[x] = f_canon(f_mul(u2d(a[x]) - v[e], pinv, L.qd, L.qinv), L.qd, L.qinv);
+    // |acc - v| <= 3.2q, |P^-1| <= q/2
+    double w = f_mul(u2d(a[x]) - v[e], pinv, L.qd, L.qinv);
+    if (ta) {  // HMUL: this component's tensor term, a0 b0 or a0 b1 + a1 b0
+      const double a0 = u2d(ta[r0 + x]);
+      if (comp == 0)
+        w += f_mul(a0, u2d(tb2[r0 + x]), L.qd, L.qinv);
+      else
+        w += f_mul(a0, u2d(tb2[r1 + x]), L.qd, L.qinv) + f_mul(u2d(ta[r1 + x]), u2d(tb2[r0 + x]), L.qd, L.qinv);
+    }
+    o[x] = f_canon(w, L.qd, L.qinv);
   }
 }
 
@@ -823,7 +875,8 @@ __device__ __forceinline__ void stage_twiddles(T* tw, const T* table, uint32_t B
 template <int LOGM, int LOGE>
 __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4 : 1) void k_moddown_km_blocks(
     DevTables tb, const uint64_t* d, const uint64_t* ext1, const uint64_t* evk, const uint64_t* t2, uint64_t* out,
-    int j0, int j1, int nslots, int slot_stride, int tgt0, int ntgt, int items) {
+    int j0, int j1, int nslots, int slot_stride, int tgt0, int ntgt, int items, const uint64_t* ta,
+    const uint64_t* tb2) {
   using B = BlockNtt<LOGM, LOGE>;
   extern __shared__ uint64_t lds[];
   double* ld = reinterpret_cast<double*>(lds);
@@ -920,13 +973,15 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
     }
   }
   const double pinv = tb.dn_pinv_d[i];
-  uint64_t* o0 = out + (((size_t)item * 2 + 0) * ell + i) * N + boff;
-  uint64_t* o1 = out + (((size_t)item * 2 + 1) * ell + i) * N + boff;
+  const size_t r0 = (((size_t)item * 2 + 0) * ell + i) * N + boff, r1 = (((size_t)item * 2 + 1) * ell + i) * N + boff;
 #pragma unroll
   for (int e = 0; e < B::E; ++e) {
     const int x = B::cl_pos(tid, e);
-    o0[x] = f_canon(f_mul(f_red(s0[e], L.qd, L.qinv), pinv, L.qd, L.qinv), L.qd, L.qinv);
-    o1[x] = f_canon(f_mul(f_red(s1[e], L.qd, L.qinv), pinv, L.qd, L.qinv), L.qd, L.qinv);
+    double v0 = f_mul(f_red(s0[e], L.qd, L.qinv), pinv, L.qd, L.qinv);
+    double v1 = f_mul(f_red(s1[e], L.qd, L.qinv), pinv, L.qd, L.qinv);
+    if (ta) add_tensor(L, ta, tb2, r0 + x, r1 + x, v0, v1);  // HMUL: |v| stays below 3q
+    out[r0 + x] = f_canon(v0, L.qd, L.qinv);
+    out[r1 + x] = f_canon(v1, L.qd, L.qinv);
   }
 }
 
@@ -1306,11 +1361,23 @@ struct ModdownColsMx {
 template <int LOGM, int LOGE>
 struct ModdownBlocks {
   static hipError_t run(const DevTables& tb, const uint64_t* t2, const uint64_t* acc, uint64_t* out, int tgt0,
-                        int tgt1, int items, hipStream_t s) {
+                        int tgt1, int items, const uint64_t* ta, const uint64_t* tb2, hipStream_t s) {
     using B = BlockNtt<LOGM, LOGE>;
     allow_lds<k_moddown_blocks<LOGM, LOGE>>();
     k_moddown_blocks<LOGM, LOGE><<<dim3(xcd_grid((tgt1 - tgt0) << (tb.log_n - LOGM), items * 2)), dim3(B::T),
-                                   block_lds<LOGM, LOGE>(), s>>>(tb, t2, acc, out, tgt0, tgt1 - tgt0, items * 2);
+                                   block_lds<LOGM, LOGE>(), s>>>(tb, t2, acc, out, tgt0, tgt1 - tgt0, items * 2, ta,
+                                                                 tb2);
+    return hipGetLastError();
+  }
+};
+template <int LOGM, int LOGE>
+struct TensorBlocks {
+  static hipError_t run(const DevTables& tb, const uint64_t* a, const uint64_t* b, uint64_t* d2, uint64_t* t1,
+                        int items, hipStream_t s) {
+    using B = BlockNtt<LOGM, LOGE>;
+    allow_lds<k_tensor_blocks<LOGM, LOGE>>();
+    k_tensor_blocks<LOGM, LOGE><<<dim3(xcd_grid(tb.ell << (tb.log_n - LOGM), items)), dim3(B::T),
+                                  block_lds<LOGM, LOGE>(), s>>>(tb, a, b, d2, t1, items);
     return hipGetLastError();
   }
 };
@@ -1324,12 +1391,13 @@ template <int LOGM, int LOGE>
 struct ModdownKmBlocks {
   static hipError_t run(const DevTables& tb, const uint64_t* d, const uint64_t* ext1, const uint64_t* evk,
                         const uint64_t* t2, uint64_t* out, int j0, int j1, int nslots, int slot_stride, int tgt0,
-                        int tgt1, int items, hipStream_t s) {
+                        int tgt1, int items, const uint64_t* ta, const uint64_t* tb2, hipStream_t s) {
     using B = BlockNtt<LOGM, LOGE>;
     allow_lds<k_moddown_km_blocks<LOGM, LOGE>>();
     k_moddown_km_blocks<LOGM, LOGE><<<dim3(xcd_grid((tgt1 - tgt0) << (tb.log_n - LOGM), items)), dim3(B::T),
                                       km_lds<LOGM, LOGE>(), s>>>(tb, d, ext1, evk, t2, out, j0, j1, nslots,
-                                                                    slot_stride, tgt0, tgt1 - tgt0, items);
+                                                                    slot_stride, tgt0, tgt1 - tgt0, items, ta,
+                                                                    tb2);
     return hipGetLastError();
   }
 };
@@ -1388,6 +1456,11 @@ hipError_t launch_intt_blocks(const DevTables& tb, int log_r, const uint64_t* sr
   return by_logm<BlocksInv>(tb.log_n - log_r, tb, src, dst, 0, nlimbs, items, 0, s);
 }
 
+hipError_t launch_tensor_blocks(const DevTables& tb, int log_r, const uint64_t* a, const uint64_t* b, uint64_t* d2,
+                                uint64_t* t1, int items, hipStream_t s) {
+  return by_logm<TensorBlocks>(tb.log_n - log_r, tb, a, b, d2, t1, items, s);
+}
+
 hipError_t launch_modup_cols(const DevTables& tb, int log_r, const uint64_t* t1, uint64_t* ext1, int j0, int nj,
                              int nslots, int slot_stride, int tgt0, int tgt1, int items, int mfma, hipStream_t s) {
   if (mfma)
@@ -1406,9 +1479,10 @@ hipError_t launch_keymult_blocks(const DevTables& tb, int log_r, const uint64_t*
 
 hipError_t launch_moddown_km_blocks(const DevTables& tb, int log_r, const uint64_t* d, const uint64_t* ext1,
                                     const uint64_t* evk, const uint64_t* t2, uint64_t* out, int j0, int j1,
-                                    int nslots, int slot_stride, int tgt0, int tgt1, int items, hipStream_t s) {
+                                    int nslots, int slot_stride, int tgt0, int tgt1, int items, const uint64_t* ta,
+                                    const uint64_t* tb2, hipStream_t s) {
   return by_logm_k3<ModdownKmBlocks>(tb.log_n - log_r, tb, d, ext1, evk, t2, out, j0, j1, nslots, slot_stride, tgt0,
-                                     tgt1, items, s);
+                                     tgt1, items, ta, tb2, s);
 }
 
 hipError_t launch_moddown_cols(const DevTables& tb, int log_r, const uint64_t* accp, uint64_t* t2, int tgt0,
@@ -1418,8 +1492,9 @@ hipError_t launch_moddown_cols(const DevTables& tb, int log_r, const uint64_t* a
 }
 
 hipError_t launch_moddown_blocks(const DevTables& tb, int log_r, const uint64_t* t2, const uint64_t* acc,
-                                 uint64_t* out, int tgt0, int tgt1, int items, hipStream_t s) {
-  return by_logm<ModdownBlocks>(tb.log_n - log_r, tb, t2, acc, out, tgt0, tgt1, items, s);
+                                 uint64_t* out, int tgt0, int tgt1, int items, const uint64_t* ta,
+                                 const uint64_t* tb2, hipStream_t s) {
+  return by_logm<ModdownBlocks>(tb.log_n - log_r, tb, t2, acc, out, tgt0, tgt1, items, ta, tb2, s);
 }
 
 hipError_t launch_ext_blocks(const DevTables& tb, int log_r, uint64_t* ext, int items, hipStream_t s) {

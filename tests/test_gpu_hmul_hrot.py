@@ -43,7 +43,11 @@ def test_hmul_and_hrot_match_oracle(ks, dnum, log_n, ell, levels):
         P = Pt.at_level(level)
         a, b = _ct(P, batch, 10 + level), _ct(P, batch, 20 + level)
         ref = oracle.hmul(P, a, b, host(mk).reshape(P.key_shape), batch)
+        # fused plans fold the tensor product into the KeySwitch's first and
+        # last passes (digit-parallel and digit-serial last passes, split
+        # batches); STAGED runs it as separate kernels
         for plan in (None, ks.make_plan(ks.DPOB, 1, 2, mfma=True), ks.make_plan(ks.DSOC, min(2, level), 3),
+                     ks.make_plan(ks.DSOB, 1, 0), ks.make_plan(ks.DPOC, min(2, level), 1, split=True),
                      ks.make_plan(ks.STAGED)):
             out = empty(ref.shape)
             G.hmul(dev(a), dev(b), mk, out, batch, G.eval_workspace(batch, plan), plan)
