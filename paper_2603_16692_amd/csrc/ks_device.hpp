@@ -255,7 +255,16 @@ __device__ __forceinline__ void sub_inv(const Ar& A, typename Ar::T* x, uint32_t
   }
 }
 
-__device__ __forceinline__ int lds_pad(int x) { return x + (x >> 4); }
+// LDS word of element x: one pad word after every 16, so that the strided
+// round layouts hit distinct banks.
+__device__ __forceinline__ int lds_pad(int x) { return x + (int)((unsigned)x >> 4); }
+
+// lds_pad(x0 + d) = lds_pad(x0) + d + (d >> 4) for the strides d = j*L of a
+// round layout (L a power of two, x0 = pos(r, tid, u, 0)): x0 mod 16 plus
+// d mod 16 never reaches 16, since either 16 divides d, or x0 mod 16 < L and
+// d mod 16 <= 16 - L, or the whole group of 2^k*L <= 16 elements shares its
+// 16-word line. The per-register offsets are then compile-time constants.
+__device__ constexpr int pad_step(int d) { return d + (d >> 4); }
 
 // Transform stages log_r .. log_n-1 (forward) of one contiguous block of
 // M = 2^LOGM elements, block index b in [0, R). T = M / E threads, E = 2^LOGE
@@ -312,19 +321,24 @@ struct BlockNtt {
 #pragma unroll
     for (int u = 0; u < (E >> K); ++u) sub_inv<K>(A, x + u * (1 << K), base(r, tid, u, B0));
   }
+  __device__ static constexpr int round_l(int r) { return M >> (round_s0(r) + round_k(r)); }
   template <int K, class V>
   __device__ static __forceinline__ void to_lds(const V* x, V* lds, int r, int tid) {
 #pragma unroll
-    for (int u = 0; u < (E >> K); ++u)
+    for (int u = 0; u < (E >> K); ++u) {
+      V* b = lds + lds_pad(pos(r, tid, u, 0));
 #pragma unroll
-      for (int j = 0; j < (1 << K); ++j) lds[lds_pad(pos(r, tid, u, j))] = x[u * (1 << K) + j];
+      for (int j = 0; j < (1 << K); ++j) b[pad_step(j * round_l(r))] = x[u * (1 << K) + j];
+    }
   }
   template <int K, class V>
   __device__ static __forceinline__ void from_lds(V* x, const V* lds, int r, int tid) {
 #pragma unroll
-    for (int u = 0; u < (E >> K); ++u)
+    for (int u = 0; u < (E >> K); ++u) {
+      const V* b = lds + lds_pad(pos(r, tid, u, 0));
 #pragma unroll
-      for (int j = 0; j < (1 << K); ++j) x[u * (1 << K) + j] = lds[lds_pad(pos(r, tid, u, j))];
+      for (int j = 0; j < (1 << K); ++j) x[u * (1 << K) + j] = b[pad_step(j * round_l(r))];
+    }
   }
 
   // Forward: x enters in FR, leaves in CL. B0 = R + b. Starts with a barrier
@@ -342,16 +356,18 @@ struct BlockNtt {
       to_lds<LOGE>(x, lds, r, tid);
     }
     __syncthreads();
+    const typename Ar::T* c = lds + lds_pad(tid);  // CL: x = tid + i*T
 #pragma unroll
-    for (int i = 0; i < E; ++i) x[i] = lds[lds_pad(cl_pos(tid, i))];
+    for (int i = 0; i < E; ++i) x[i] = c[pad_step(i * T)];
   }
 
   // Inverse: x enters in CL, leaves in FR.
   template <class Ar>
   __device__ static void inv(const Ar& A, typename Ar::T* x, typename Ar::T* lds, int tid, uint32_t B0) {
     __syncthreads();
+    typename Ar::T* c = lds + lds_pad(tid);
 #pragma unroll
-    for (int i = 0; i < E; ++i) lds[lds_pad(cl_pos(tid, i))] = x[i];
+    for (int i = 0; i < E; ++i) c[pad_step(i * T)] = x[i];
 #pragma unroll
     for (int r = NR - 1; r >= 1; --r) {
       __syncthreads();
