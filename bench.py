@@ -39,8 +39,8 @@ OP_METRIC = {"keyswitch": "KeySwitch/s", "hmul": "HMUL/s", "hrot": "HROT/s"}
 # (sha256 below) and for the same workload and plan; otherwise "traffic" is null.
 # The rocprofv3 summaries it comes from are under profiles/.
 TRAFFIC = {"workload": "c2", "plan": "Plan(DPOB, chunks=1, log_r=4, mfma)", "kernel": "moddown_blocks",
-           "fetch_kib": 509072.4, "fetch_scale": 2.0, "write_kib": 344064.0, "write_scale": 1.0,
-           "sources_sha256": "4f7c654442771b3337e247b108b3596ca26b2e027b42100c3bcdb137eb594d3c"}
+           "fetch_kib": 467827.6, "fetch_scale": 2.0, "write_kib": 262144.0, "write_scale": 1.0,
+           "sources_sha256": "7b3f4d075c72764311988a37a620b7e4734d01ab7a65c06b17c662ebb90146d0"}
 TRAFFIC_SOURCES = ["paper_2603_16692_amd/csrc/ks_kernels.hip", "paper_2603_16692_amd/csrc/ks_device.hpp"]
 
 
