@@ -225,7 +225,12 @@ struct ArF {
 // index of the subproblem at its first stage (the butterfly tree of the
 // transform numbers node u's children 2u and 2u+1).
 // Local stages alternate reducing (even rho) and lazy (odd rho) butterflies.
-template <int K, class Ar>
+//
+// PS >= 0: the table is a block's staged copy (base = 2^PS + p) whose stages
+// PS.. are stored group-major, entry (p << rho) + g of stage PS + rho at
+// 2^(PS + rho) + (g << PS) + p, so that the lanes of a wave (consecutive p)
+// read consecutive words.
+template <int K, int PS = -1, class Ar>
 __device__ __forceinline__ void sub_fwd(const Ar& A, typename Ar::T* x, uint32_t base) {
 #pragma unroll
   for (int rho = 0; rho < K; ++rho) {
@@ -233,7 +238,9 @@ __device__ __forceinline__ void sub_fwd(const Ar& A, typename Ar::T* x, uint32_t
 #pragma unroll
     for (int j = 0; j < (1 << K); ++j) {
       if (j & dist) continue;
-      const uint32_t idx = (base << rho) + (uint32_t)(j >> (K - rho));
+      const uint32_t g = (uint32_t)(j >> (K - rho));
+      const uint32_t idx = PS < 0 ? (base << rho) + g
+                                  : base + ((1u << (PS + rho)) - (1u << PS)) + (g << (PS < 0 ? 0 : PS));
       if (rho & 1)
         A.fwd_lazy(x[j], x[j + dist], idx);
       else
@@ -311,11 +318,13 @@ struct BlockNtt {
   __device__ static __forceinline__ int fr_pos(int tid, int i) { return pos(0, tid, i >> K1, i & ((1 << K1) - 1)); }
   __device__ static __forceinline__ int cl_pos(int tid, int i) { return tid + i * T; }
 
-  template <int K, class Ar>
+  template <int K, int PS = -1, class Ar>
   __device__ static __forceinline__ void round_fwd(const Ar& A, typename Ar::T* x, int r, int tid, uint32_t B0) {
 #pragma unroll
-    for (int u = 0; u < (E >> K); ++u) sub_fwd<K>(A, x + u * (1 << K), base(r, tid, u, B0));
+    for (int u = 0; u < (E >> K); ++u) sub_fwd<K, PS>(A, x + u * (1 << K), base(r, tid, u, B0));
   }
+  // First stage of the last round, where every thread has its own twiddles.
+  static constexpr int LAST_S0 = LOGM - LOGE;
   template <int K, class Ar>
   __device__ static __forceinline__ void round_inv(const Ar& A, typename Ar::T* x, int r, int tid, uint32_t B0) {
 #pragma unroll
@@ -342,8 +351,10 @@ struct BlockNtt {
   }
 
   // Forward: x enters in FR, leaves in CL. B0 = R + b. Starts with a barrier
-  // so the LDS block may be reused right after a previous call.
-  template <class Ar>
+  // so the LDS block may be reused right after a previous call. STAGED: the
+  // twiddles are a staged copy (B0 = 1) with the last round's stages stored
+  // group-major (sub_fwd with PS = LAST_S0).
+  template <bool STAGED = false, class Ar>
   __device__ static void fwd(const Ar& A, typename Ar::T* x, typename Ar::T* lds, int tid, uint32_t B0) {
     round_fwd<K1>(A, x, 0, tid, B0);
     __syncthreads();
@@ -352,7 +363,10 @@ struct BlockNtt {
     for (int r = 1; r < NR; ++r) {
       __syncthreads();
       from_lds<LOGE>(x, lds, r, tid);
-      round_fwd<LOGE>(A, x, r, tid, B0);
+      if (STAGED && r == NR - 1)
+        round_fwd<LOGE, LAST_S0>(A, x, r, tid, B0);
+      else
+        round_fwd<LOGE>(A, x, r, tid, B0);
       to_lds<LOGE>(x, lds, r, tid);
     }
     __syncthreads();

@@ -67,12 +67,12 @@ inline unsigned xcd_grid(int ntiles, int items) { return (unsigned)(((ntiles + 7
 // runs several transforms would otherwise keep every LDS and twiddle address
 // of all rounds live from the first transform to the last, which costs more
 // registers than recomputing them.
-template <class B, class Ar>
+template <class B, bool STAGED = false, class Ar>
 __device__ __forceinline__ void fwd_opaque(const Ar& A, typename Ar::T* v, typename Ar::T* ld, int tid,
                                            uint32_t B0) {
   int t = tid;
   asm volatile("" : "+v"(t));
-  B::fwd(A, v, ld, t, B0);
+  B::template fwd<STAGED>(A, v, ld, t, B0);
 }
 template <class B, class Ar>
 __device__ __forceinline__ void inv_opaque(const Ar& A, typename Ar::T* v, typename Ar::T* ld, int tid,
@@ -851,14 +851,22 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_moddown_blocks(DevTabl
 
 // The twiddles one block pass reads, staged in LDS: entry x in [1, M) is
 // table entry ((R + b) << s) + x - 2^s with s = floor(log2 x), the twiddle of
-// local stage s and group x - 2^s of block b. BlockNtt with B0 = 1 and this
-// table computes what it computes with B0 = R + b and the global table.
-template <int LOGM, class T>
+// local stage s and group x - 2^s of block b. Stages s >= PS (the last round
+// of the forward pass) are stored group-major: group (p << (s - PS)) + g at
+// 2^s + (g << PS) + p. BlockNtt::fwd<true> with B0 = 1 and this table
+// computes what BlockNtt::fwd computes with B0 = R + b and the global table.
+template <int LOGM, int PS, class T>
 __device__ __forceinline__ void stage_twiddles(T* tw, const T* table, uint32_t B0, int tid, int nthreads) {
   for (int x = tid; x < (1 << LOGM); x += nthreads) {
     if (x == 0) continue;
     const int s = 31 - __clz(x);
-    tw[x] = table[(B0 << s) + (uint32_t)(x - (1 << s))];
+    const uint32_t grp = (uint32_t)(x - (1 << s));
+    uint32_t pos = (uint32_t)x;
+    if (s >= PS) {  // grp = (p << rho) + g
+      const int rho = s - PS;
+      pos = (1u << s) + ((grp & ((1u << rho) - 1)) << PS) + (grp >> rho);
+    }
+    tw[pos] = table[(B0 << s) + grp];
   }
 }
 
@@ -918,7 +926,7 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
     for (int e = 0; e < B::E; ++e) cur[e] = u2d(src[B::fr_pos(tid, e)]);
   }
   if constexpr (TWL) {
-    stage_twiddles<LOGM>(tw, tb.twf_d + (size_t)i * N, (uint32_t)(R + b), tid, B::T);
+    stage_twiddles<LOGM, B::LAST_S0>(tw, tb.twf_d + (size_t)i * N, (uint32_t)(R + b), tid, B::T);
     __syncthreads();
   }
   {
@@ -926,14 +934,14 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
 #pragma unroll
     for (int e = 0; e < B::E; ++e) nxt[e] = u2d(src[B::fr_pos(tid, e)]);
   }
-  fwd_opaque<B>(A, cur, ld, tid, B0);
+  fwd_opaque<B, TWL>(A, cur, ld, tid, B0);
 #pragma unroll
   for (int e = 0; e < B::E; ++e) {
     s0[e] = -cur[e];
     cur[e] = nxt[e];
   }
   if (DEEP && j0 < j1) load_digit(j0, nxt);
-  fwd_opaque<B>(A, cur, ld, tid, B0);
+  fwd_opaque<B, TWL>(A, cur, ld, tid, B0);
 #pragma unroll
   for (int e = 0; e < B::E; ++e) s1[e] = -cur[e];
   for (int j = j0; j < j1; ++j) {
@@ -954,7 +962,7 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
     } else {
       load_digit(j, cur);
     }
-    if (j != own) fwd_opaque<B>(A, cur, ld, tid, B0);
+    if (j != own) fwd_opaque<B, TWL>(A, cur, ld, tid, B0);
     if constexpr (!DEEP) {
 #pragma unroll
       for (int e = 0; e < B::E; ++e) w1[e] = u2d(k1[B::cl_pos(tid, e)]);
