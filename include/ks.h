@@ -82,8 +82,9 @@ typedef struct {
    into balanced signed bytes, the int32 partial sums of each byte weight are
    folded back modulo the target prime. The output is identical to the
    default (FP64 / 64-bit integer) BConv. Supported when every digit and P
-   have at most 16 primes and log_r <= 4 (ks_keyswitch returns KS_EUNSUP
-   otherwise). */
+   have at most 16 primes, log_r <= 5 and the packed digits of a workgroup,
+   ceil(max(alpha, k) / 4) * 2^log_r * 2 KB, fit in the 160 KB of LDS
+   (ks_keyswitch returns KS_EUNSUP otherwise). */
 #define KS_PLAN_MFMA_BCONV 1
 
 /* Plan flag: with batch >= 2, run items [batch/2, batch) on a second stream

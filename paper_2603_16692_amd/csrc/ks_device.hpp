@@ -350,6 +350,28 @@ struct BlockNtt {
     }
   }
 
+  // Whether the layout of round q and the next one hold the same elements in
+  // each wavefront. In a round whose groups are at most 64 elements apart
+  // (L <= 64) with one register subproblem per thread, the 64 threads of wave
+  // w hold exactly elements [64E w, 64E (w + 1)), and so in every later
+  // round: the exchange between such rounds touches only the wave's own LDS
+  // words, and a wave-local ordering point replaces the workgroup barrier.
+  __device__ static constexpr bool wave_local(int q) {
+    return T <= 64 || ((q >= 1 || K1 == LOGE) && round_l(q) <= 64);
+  }
+  // Orders the LDS stores before this point against the loads after it: for
+  // the whole workgroup, or (local) for this wavefront, whose LDS accesses
+  // execute in order.
+  __device__ static __forceinline__ void exchange_sync(bool local) {
+    if (local) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+      __syncthreads();
+    }
+  }
+
   // Forward: x enters in FR, leaves in CL. B0 = R + b. Starts with a barrier
   // so the LDS block may be reused right after a previous call. STAGED: the
   // twiddles are a staged copy (B0 = 1) with the last round's stages stored
@@ -361,7 +383,7 @@ struct BlockNtt {
     to_lds<K1>(x, lds, 0, tid);
 #pragma unroll
     for (int r = 1; r < NR; ++r) {
-      __syncthreads();
+      exchange_sync(wave_local(r - 1));
       from_lds<LOGE>(x, lds, r, tid);
       if (STAGED && r == NR - 1)
         round_fwd<LOGE, LAST_S0>(A, x, r, tid, B0);
@@ -384,12 +406,12 @@ struct BlockNtt {
     for (int i = 0; i < E; ++i) c[pad_step(i * T)] = x[i];
 #pragma unroll
     for (int r = NR - 1; r >= 1; --r) {
-      __syncthreads();
+      exchange_sync(r < NR - 1 && wave_local(r));  // the first read follows the CL stores
       from_lds<LOGE>(x, lds, r, tid);
       round_inv<LOGE>(A, x, r, tid, B0);
       to_lds<LOGE>(x, lds, r, tid);
     }
-    __syncthreads();
+    exchange_sync(wave_local(0));
     from_lds<K1>(x, lds, 0, tid);
     round_inv<K1>(A, x, 0, tid, B0);
   }

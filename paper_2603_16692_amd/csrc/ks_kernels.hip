@@ -888,7 +888,9 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
   using B = BlockNtt<LOGM, LOGE>;
   extern __shared__ uint64_t lds[];
   double* ld = reinterpret_cast<double*>(lds);
-  constexpr bool TWL = (B::LDS_WORDS + B::M) * sizeof(double) <= 160 * 1024;
+  // Staged twiddles up to blocks of 2^12 (beyond, the extra LDS would leave
+  // one workgroup per CU, which costs more than the table reads it saves).
+  constexpr bool TWL = LOGM <= 12;
   double* tw = ld + B::LDS_WORDS;
   const size_t N = (size_t)1 << tb.log_n;
   const int R = (int)(N >> LOGM);
@@ -1178,7 +1180,8 @@ hipError_t by_logr(int log_r, A... a) {
   }
 }
 
-// The MFMA column kernels hold 2R values per lane: at most 16 rows.
+// The MFMA column kernels hold 2R values per lane: at most 32 rows (at 32 rows
+// with two waves per SIMD).
 template <template <int> class F, typename... A>
 hipError_t by_logr_mx(int log_r, A... a) {
   switch (log_r) {
@@ -1187,6 +1190,7 @@ hipError_t by_logr_mx(int log_r, A... a) {
     case 2: return F<2>::run(a...);
     case 3: return F<3>::run(a...);
     case 4: return F<4>::run(a...);
+    case 5: return F<5>::run(a...);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1392,8 +1396,7 @@ struct TensorBlocks {
 template <int LOGM, int LOGE>
 size_t km_lds() {
   using B = BlockNtt<LOGM, LOGE>;
-  const size_t with_tw = sizeof(double) * (B::LDS_WORDS + B::M);
-  return with_tw <= 160 * 1024 ? with_tw : block_lds<LOGM, LOGE>();
+  return LOGM <= 12 ? sizeof(double) * (B::LDS_WORDS + B::M) : block_lds<LOGM, LOGE>();
 }
 template <int LOGM, int LOGE>
 struct ModdownKmBlocks {
@@ -1439,8 +1442,8 @@ struct PBlocksInv {
 int stage_cap(int count, int log_r) { return (size_t)count * ((size_t)1 << log_r) * 64 * 8 <= 160 * 1024 ? 1 : 0; }
 
 int mx_ok(const DevTables& tb, int log_r) {
-  // at most 16 sources (the partial-sum bound), 16 rows per column (registers), LDS
-  return tb.up_nm <= 4 && tb.dn_nm <= 4 && log_r <= 4 && mx_lds_bytes(tb.up_nm, log_r) <= 160 * 1024 &&
+  // at most 16 sources (the partial-sum bound), 32 rows per column (registers), LDS
+  return tb.up_nm <= 4 && tb.dn_nm <= 4 && log_r <= 5 && mx_lds_bytes(tb.up_nm, log_r) <= 160 * 1024 &&
          mx_lds_bytes(tb.dn_nm, log_r) <= 160 * 1024;
 }
 

@@ -7,7 +7,8 @@ from paper_2603_16692_amd import autotune
 
 class FakeParams:
     """Accepts a plan when libks would: NTT split within the compiled range,
-    chunks within ell, the MFMA BConv only up to 16 rows per column."""
+    chunks within ell, the MFMA BConv only up to 32 rows per column and
+    16 sources, with its packed digits within the 160 KB of LDS."""
 
     def __init__(self, dnum, log_n, ell):
         self.dnum, self.log_n, self.ell = dnum, log_n, ell
@@ -21,7 +22,8 @@ class FakeParams:
         log_m = self.log_n - plan.log_r
         if plan.log_r > 5 or log_m < 3 or log_m > 14:
             raise ks.KsError(ks.KS_EUNSUP, "split")
-        if (plan.flags & ks.PLAN_MFMA_BCONV) and (plan.log_r > 4 or self.alpha > 16):
+        nm = -(-max(self.alpha, self.k) // 4)
+        if (plan.flags & ks.PLAN_MFMA_BCONV) and (nm > 4 or nm * (32 << plan.log_r) * 64 > 160 * 1024):
             raise ks.KsError(ks.KS_EUNSUP, "mfma")
         if plan.dataflow in (ks.DSOC, ks.DPOC) and not 1 <= plan.chunks <= min(64, self.ell):
             raise ks.KsError(ks.KS_EUNSUP, "chunks")
@@ -36,7 +38,10 @@ def test_candidates_cover_both_bconv_variants():
     plans = autotune.candidate_plans(P, 8)
     keys = {p.key() for p in plans}
     assert (ks.DPOB, 1, 4, ks.PLAN_MFMA_BCONV) in keys and (ks.DPOB, 1, 4, 0) in keys
-    assert (ks.DPOB, 1, 5, 0) in keys and (ks.DPOB, 1, 5, ks.PLAN_MFMA_BCONV) not in keys
+    assert (ks.DPOB, 1, 5, 0) in keys and (ks.DPOB, 1, 5, ks.PLAN_MFMA_BCONV) in keys
+    # 32 rows of 12-prime digits exceed the LDS of the MFMA BConv
+    wide = {p.key() for p in autotune.candidate_plans(FakeParams(1, 12, 12), 1)}
+    assert (ks.DPOB, 1, 4, ks.PLAN_MFMA_BCONV) in wide and (ks.DPOB, 1, 5, ks.PLAN_MFMA_BCONV) not in wide
     assert all(p.log_r >= 2 for p in plans)  # blocks of at most 2^14
     assert len(keys) == len(plans)
     # the batch split over two streams is a candidate only when there are two items
@@ -74,7 +79,7 @@ def test_table_lookup_exact_then_nearest_batch():
     # another parameter set finds nothing
     assert autotune.plan_for(FakeParams(2, 15, 10), 8, table) is None
     # a stored plan the parameters do not accept is skipped
-    bad = {autotune._cache_key(P, 8): {"plan": [ks.DPOB, 1, 5, ks.PLAN_MFMA_BCONV], "ms": 1.0, "name": "z"}}
+    bad = {autotune._cache_key(P, 8): {"plan": [ks.DPOB, 1, 9, ks.PLAN_MFMA_BCONV], "ms": 1.0, "name": "z"}}
     assert autotune.plan_for(P, 8, bad) is None
 
 

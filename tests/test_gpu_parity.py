@@ -118,10 +118,9 @@ def _plans(ks, P, log_n):
         for df, chunks in [(ks.DSOB, 1), (ks.DPOB, 1), (ks.DSOC, 2), (ks.DPOC, 3), (ks.STAGED, 1)]:
             chunks = min(chunks, P.ell)
             plans.append(ks.make_plan(df, chunks, log_r))
-            if log_r <= 4:  # the int8-MFMA BConv
-                plans.append(ks.make_plan(df, chunks, log_r, mfma=True))
+            plans.append(ks.make_plan(df, chunks, log_r, mfma=True))  # the int8-MFMA BConv
             # the batch over two streams (3 items: 1 + 2)
-            plans.append(ks.make_plan(df, chunks, log_r, mfma=log_r <= 4, split=True))
+            plans.append(ks.make_plan(df, chunks, log_r, mfma=True, split=True))
     return plans
 
 
@@ -160,7 +159,8 @@ def test_keyswitch_benchmark_sizes(ks, name):
     dd, ee = dev(d), dev(evk)
     plans = [None, ks.make_plan(ks.DSOB), ks.make_plan(ks.DPOC, 4), ks.make_plan(ks.DSOC, 2),
              ks.make_plan(ks.DPOB, 1, 4, mfma=True), ks.make_plan(ks.DSOC, 3, 3, mfma=True),
-             ks.make_plan(ks.STAGED, 1, 4, mfma=True), ks.make_plan(ks.DPOB, 1, 4, mfma=True, split=True)]
+             ks.make_plan(ks.STAGED, 1, 4, mfma=True), ks.make_plan(ks.DPOB, 1, 4, mfma=True, split=True),
+             ks.make_plan(ks.DPOB, 1, 5, mfma=True)]
     for plan in plans:
         out = empty(ref.shape)
         ws = G.workspace(batch, plan)
@@ -236,8 +236,8 @@ def test_argument_errors(ks):
     with pytest.raises(ks.KsError) as e:
         G.keyswitch(d, evk, out, 1, ws, ks.make_plan(ks.DPOB, 1, 9))
     assert e.value.code == ks.KS_EUNSUP
-    with pytest.raises(ks.KsError) as e:  # the MFMA BConv holds at most 16 rows per lane
-        G.keyswitch(d, evk, out, 1, ws, ks.make_plan(ks.DPOB, 1, 5, mfma=True))
+    with pytest.raises(ks.KsError) as e:  # 32 rows of 12 sources exceed the MFMA BConv's LDS
+        ks.KsParams(1, 12, 12).workspace_bytes(1, ks.make_plan(ks.DPOB, 1, 5, mfma=True))
     assert e.value.code == ks.KS_EUNSUP
     with pytest.raises(ks.KsError) as e:  # ... and at most 16 sources per BConv
         ks.KsParams(1, 10, 20).workspace_bytes(1, ks.make_plan(ks.DPOB, 1, 2, mfma=True))
