@@ -1210,15 +1210,18 @@ hipError_t by_logm(int log_m, A... a) {
 }
 
 // KeyMult keeps two accumulators per element across the digits, so its block
-// pass runs with 8 elements per thread below M = 2^13 (16 from there on, where 8
-// would need more than 128 registers at 1024 threads).
-constexpr int loge_k3(int logm) { return logm >= 13 ? 4 : (logm >= 6 ? 3 : (logm >= 4 ? 2 : 1)); }
+// passes run with 8 elements per thread up to M = 2^13 (1024 threads at 2^13)
+// and 16 beyond. K5 also holds its prefetched inputs and key blocks: 8
+// elements per thread up to 2^12, 16 from 2^13 on (at 1024 threads it would
+// spill).
+constexpr int loge_k3(int logm) { return logm >= 14 ? 4 : (logm >= 6 ? 3 : (logm >= 4 ? 2 : 1)); }
+constexpr int loge_k5(int logm) { return logm >= 13 ? 4 : loge_k3(logm); }
 
-template <template <int, int> class F, typename... A>
+template <template <int, int> class F, bool K5 = false, typename... A>
 hipError_t by_logm_k3(int log_m, A... a) {
   switch (log_m) {
 #define KS_CASE(m) \
-  case m: return F<m, loge_k3(m)>::run(a...);
+  case m: return F<m, K5 ? loge_k5(m) : loge_k3(m)>::run(a...);
     KS_CASE(3) KS_CASE(4) KS_CASE(5) KS_CASE(6) KS_CASE(7) KS_CASE(8) KS_CASE(9) KS_CASE(10) KS_CASE(11)
     KS_CASE(12) KS_CASE(13) KS_CASE(14)
 #undef KS_CASE
@@ -1492,7 +1495,7 @@ hipError_t launch_moddown_km_blocks(const DevTables& tb, int log_r, const uint64
                                     const uint64_t* evk, const uint64_t* t2, uint64_t* out, int j0, int j1,
                                     int nslots, int slot_stride, int tgt0, int tgt1, int items, const uint64_t* ta,
                                     const uint64_t* tb2, hipStream_t s) {
-  return by_logm_k3<ModdownKmBlocks>(tb.log_n - log_r, tb, d, ext1, evk, t2, out, j0, j1, nslots, slot_stride, tgt0,
+  return by_logm_k3<ModdownKmBlocks, true>(tb.log_n - log_r, tb, d, ext1, evk, t2, out, j0, j1, nslots, slot_stride, tgt0,
                                      tgt1, items, ta, tb2, s);
 }
 
