@@ -39,8 +39,8 @@ OP_METRIC = {"keyswitch": "KeySwitch/s", "hmul": "HMUL/s", "hrot": "HROT/s"}
 # (sha256 below) and for the same workload and plan; otherwise "traffic" is null.
 # The rocprofv3 summaries it comes from are under profiles/.
 TRAFFIC = {"workload": "c2", "plan": "Plan(DPOB, chunks=1, log_r=4, mfma)", "kernel": "moddown_blocks",
-           "fetch_kib": 467827.6, "fetch_scale": 2.0, "write_kib": 262144.0, "write_scale": 1.0,
-           "sources_sha256": "7b3f4d075c72764311988a37a620b7e4734d01ab7a65c06b17c662ebb90146d0"}
+           "fetch_kib": 467752.1, "fetch_scale": 2.0, "write_kib": 262144.0, "write_scale": 1.0,
+           "sources_sha256": "47cd2ebbc36d334886ce950fe5644026c2bcd911445ae54aef1a1da844c1838d"}
 TRAFFIC_SOURCES = ["paper_2603_16692_amd/csrc/ks_kernels.hip", "paper_2603_16692_amd/csrc/ks_device.hpp"]
 
 
@@ -125,8 +125,8 @@ def percentile(xs, p):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--batch", type=int, default=0, help="override the workload's batch size")
     ap.add_argument("--op", default="keyswitch", choices=["keyswitch", "hmul", "hrot"],

@@ -62,9 +62,13 @@ class Scheduler:
     """Admission by HBM footprint, per-set FIFO batching, a fixed number of slots."""
 
     def __init__(self, executor: Executor, hbm_budget: int, max_batch: Dict[str, int], slots: int = 2,
-                 clock=time.perf_counter):
+                 clock=time.perf_counter, keep_results: bool = True):
+        """keep_results=False drops each result once its request completes (a
+        server hands it back to the client; holding every output of a long
+        request stream would fill the device memory)."""
         if slots < 1:
             raise ValueError("need at least one slot")
+        self.keep_results = keep_results
         self.ex = executor
         self.budget = hbm_budget
         self.max_batch = dict(max_batch)
@@ -101,7 +105,7 @@ class Scheduler:
             if self.ex.poll(h):
                 now = self.clock()
                 for r, res in zip(reqs, self.ex.finish(h)):
-                    r.result, r.done = res, now
+                    r.result, r.done = (res if self.keep_results else None), now
                     self.completed.append(r)
                 self.in_use -= fp
                 finished += 1
@@ -303,7 +307,7 @@ def serve_benchmark(n_requests: int = 4000, loads=(0.5, 0.8), slots: int = 2, bu
         for mode, mb, sl in (("batched", max_batch, slots), ("unbatched", {k: 1 for k in names}, 1)):
             reqs = [Request(i, picks[i], payloads[picks[i]][i % pool]) for i in range(n_requests)]
             ex = GpuExecutor(sets, evks, plans if mode == "batched" else {}, slots=sl)
-            sched = Scheduler(ex, int(budget_gb * (1 << 30)), mb, slots=sl)
+            sched = Scheduler(ex, int(budget_gb * (1 << 30)), mb, slots=sl, keep_results=False)
             sched.run(reqs, offs)
             torch.cuda.synchronize()
             st = latency_stats(sched.completed)

@@ -77,6 +77,17 @@ def test_results_and_budget():
     assert sched.in_use == ex.resident_bytes()
 
 
+def test_results_can_be_dropped_on_completion():
+    # a long request stream keeps no outputs alive; latencies are still recorded
+    clock = FakeClock()
+    ex = FakeExecutor(clock, {"a": 100, "b": 250})
+    sched = Scheduler(ex, hbm_budget=10000, max_batch={"a": 8, "b": 4}, slots=2, clock=clock, keep_results=False)
+    reqs, offs = make(200)
+    drive(sched, clock, reqs, offs)
+    assert len(sched.completed) == 200
+    assert all(r.result is None and r.latency is not None and r.latency > 0 for r in reqs)
+
+
 def test_fifo_within_each_set_and_batching():
     clock = FakeClock()
     ex = FakeExecutor(clock, {"a": 10, "b": 10})
