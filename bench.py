@@ -90,6 +90,14 @@ def kernel_bytes(G, plan, batch, kind):
             return 2 * B * ell * N * W + B * ext_q * N * W + B * ell * N * W + 2 * nd * ell * N * W \
                 + 2 * B * ell * N * W
         return 3 * 2 * B * ell * N * W
+    if kind == 5:    # STAGED: forward block pass of every raised limb of ext, in place
+        return 2 * B * (ext_q + ext_p) * N * W
+    if kind == 6:    # STAGED: inverse block pass of the P limbs of acc into accp
+        return 2 * 2 * B * k * N * W
+    if kind == 7:    # STAGED: digit limbs of d copied into their ext slots
+        return 2 * B * ell * N * W
+    if kind == 8:    # STAGED: element-wise KeyMult over ext [B][dnum][ell+k][N]
+        return B * nd * nl * N * W + 2 * nd * nl * N * W + 2 * B * nl * N * W
     return None
 
 
