@@ -157,8 +157,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(batch sharding across GPUs is described in DESIGN.md but not built).", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported: the KeySwitch path is "
+              "single-GPU (batch sharding across GPUs, which needs no communication, is not built).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
