@@ -190,8 +190,10 @@ int ks_hmul(const ks_params* p, const uint64_t* a, const uint64_t* b, const uint
  *   out = (sigma(c0), 0) + KeySwitch(sigma(c1)),
  * with evk the key from sigma(s) to s. In NTT form sigma permutes the slots:
  * slot t of the image is slot t' of the input with
- * 2 brv(t') + 1 = galois * (2 brv(t) + 1) mod 2N. KS_EINVAL for an even or
- * out-of-range element. out must not alias ct. */
+ * 2 brv(t') + 1 = galois * (2 brv(t) + 1) mod 2N. A fused plan gathers
+ * sigma(c1) in its first pass and adds sigma(c0) in its last; KS_STAGED runs
+ * them as kernels of their own. KS_EINVAL for an even or out-of-range
+ * element. out must not alias ct. */
 int ks_hrot(const ks_params* p, const uint64_t* ct, int galois, const uint64_t* evk, uint64_t* out, int batch,
             const ks_plan* plan, void* ws, void* stream);
 

@@ -193,7 +193,7 @@ int run_moddown(const ks_params* p, const ks_plan& plan, const uint64_t* acc, ui
   KS_TRY(traced(KS_K_PBLOCKS_INV, s, [&] { return ks::launch_pblocks_inv(tb, plan.log_r, acc, accp, batch, s); }));
   KS_TRY(traced(KS_K_MODDOWN_COLS, s, [&] { return ks::launch_moddown_cols(tb, plan.log_r, accp, t2, 0, tb.ell, batch, mx, s); }));
   KS_TRY(traced(KS_K_MODDOWN_BLOCKS, s, [&] {
-    return ks::launch_moddown_blocks(tb, plan.log_r, t2, acc, out, 0, tb.ell, batch, nullptr, nullptr, s);
+    return ks::launch_moddown_blocks(tb, plan.log_r, t2, acc, out, 0, tb.ell, batch, ks::EvalIn{}, s);
   }));
   return KS_OK;
 }
@@ -210,13 +210,12 @@ int km_kernels(const ks::DevTables& tb, int a, int b, bool q_part) {
 // BConv) and fold the Q-limb KeyMult into ModDown's last block pass, so acc_Q
 // never goes through memory.
 //
-// HMUL (ha, hb not null): d is a workspace buffer that the first pass fills
-// with the tensor term a1 b1, and ModDown's last pass adds the other tensor
-// terms (a0 b0, a0 b1 + a1 b0) to its output, so the HMUL costs no kernel
-// beyond the KeySwitch's own.
+// HMUL / HROT (ev.a not null): d is a workspace buffer that the first pass
+// fills with a1 b1 or sigma_g(c1), and ModDown's last pass adds the other
+// tensor terms (a0 b0, a0 b1 + a1 b0) or sigma_g(c0) to its output, so the
+// operation costs no kernel beyond the KeySwitch's own.
 int run_fused(const ks_params* p, const ks_plan& plan, const uint64_t* d, const uint64_t* evk, uint64_t* out,
-              int batch, char* ws, hipStream_t s, int* launches, const uint64_t* ha = nullptr,
-              const uint64_t* hb = nullptr) {
+              int batch, char* ws, hipStream_t s, int* launches, ks::EvalIn ev = ks::EvalIn{}) {
   const ks::DevTables& tb = p->tb;
   const Layout L = layout(p, batch, plan);
   uint64_t* t1 = reinterpret_cast<uint64_t*>(ws + L.t1);
@@ -228,9 +227,9 @@ int run_fused(const ks_params* p, const ks_plan& plan, const uint64_t* d, const 
   const int c = plan.chunks;
   int count = 0;
   const bool run = launches == nullptr;
-  if (run && ha)
+  if (run && ev.a)
     KS_TRY(traced(KS_K_INTT_D, s, [&] {
-      return ks::launch_tensor_blocks(tb, plan.log_r, ha, hb, const_cast<uint64_t*>(d), t1, batch, s);
+      return ks::launch_eval_blocks(tb, plan.log_r, ev, const_cast<uint64_t*>(d), t1, batch, s);
     }));
   else if (run)
     KS_TRY(traced(KS_K_INTT_D, s, [&] { return ks::launch_intt_blocks(tb, plan.log_r, d, t1, tb.ell, batch, s); }));
@@ -275,11 +274,11 @@ int run_fused(const ks_params* p, const ks_plan& plan, const uint64_t* d, const 
       if (dp)
         KS_TRY(traced(KS_K_MODDOWN_BLOCKS, s, [&] {
           return ks::launch_moddown_km_blocks(tb, plan.log_r, d, ext1, evk, t2, out, 0, tb.ndig, L.nslots, 1, a, b,
-                                              batch, ha, hb, s);
+                                              batch, ev, s);
         }));
       else
         KS_TRY(traced(KS_K_MODDOWN_BLOCKS, s, [&] {
-          return ks::launch_moddown_blocks(tb, plan.log_r, t2, acc, out, a, b, batch, ha, hb, s);
+          return ks::launch_moddown_blocks(tb, plan.log_r, t2, acc, out, a, b, batch, ev, s);
         }));
     }
     count += 2;
@@ -499,9 +498,9 @@ int ks_moddown(const ks_params* p, const uint64_t* acc, uint64_t* out, int batch
 }
 
 // One KeySwitch of `batch` items on stream s with workspace ws (no split);
-// with ha, hb (fused plans only) the HMUL of ha and hb, d its workspace buffer.
+// with ev.a (fused plans only) the HMUL or HROT of ev, d its workspace buffer.
 static int keyswitch_on(const ks_params* p, const ks_plan& pl, const uint64_t* d, const uint64_t* evk, uint64_t* out,
-                        int batch, char* ws, hipStream_t s, const uint64_t* ha, const uint64_t* hb) {
+                        int batch, char* ws, hipStream_t s, ks::EvalIn ev) {
   if (pl.dataflow == KS_STAGED) {
     const Layout L = layout(p, batch, pl);
     uint64_t* ext = reinterpret_cast<uint64_t*>(ws + L.ext);
@@ -512,15 +511,14 @@ static int keyswitch_on(const ks_params* p, const ks_plan& pl, const uint64_t* d
     return run_moddown(p, pl, acc, out, batch, reinterpret_cast<uint64_t*>(ws + L.accp),
                        reinterpret_cast<uint64_t*>(ws + L.t2), s);
   }
-  return run_fused(p, pl, d, evk, out, batch, ws, s, nullptr, ha, hb);
+  return run_fused(p, pl, d, evk, out, batch, ws, s, nullptr, ev);
 }
 
 // keyswitch_on, or for a split plan its two halves on the two streams.
 static int keyswitch_any(const ks_params* p, const ks_plan& pl, const uint64_t* d, const uint64_t* evk,
-                         uint64_t* out, int batch, char* w, hipStream_t s, const uint64_t* ha = nullptr,
-                         const uint64_t* hb = nullptr) {
+                         uint64_t* out, int batch, char* w, hipStream_t s, ks::EvalIn ev = ks::EvalIn{}) {
   int b0, rc;
-  if (!split_batch(pl, batch, b0)) return keyswitch_on(p, pl, d, evk, out, batch, w, s, ha, hb);
+  if (!split_batch(pl, batch, b0)) return keyswitch_on(p, pl, d, evk, out, batch, w, s, ev);
   // Items [b0, batch) on the second stream, after everything already on s;
   // s then waits for them, so the call still completes in stream order on s.
   const size_t N = p->hp.n, ell = p->hp.ell;
@@ -529,11 +527,12 @@ static int keyswitch_any(const ks_params* p, const ks_plan& pl, const uint64_t* 
   std::lock_guard<std::mutex> lock(const_cast<ks_params*>(p)->split);
   KS_TRY(hipEventRecord(p->fork, s));
   KS_TRY(hipStreamWaitEvent(p->side, p->fork, 0));
-  if ((rc = keyswitch_on(p, pl, d + (size_t)b0 * ell * N, evk, out + ct, batch - b0, w + ws0, p->side,
-                         ha ? ha + ct : nullptr, hb ? hb + ct : nullptr)) != KS_OK)
+  const ks::EvalIn ev1{ev.a ? ev.a + ct : nullptr, ev.b ? ev.b + ct : nullptr, ev.galois};
+  if ((rc = keyswitch_on(p, pl, d + (size_t)b0 * ell * N, evk, out + ct, batch - b0, w + ws0, p->side, ev1)) !=
+      KS_OK)
     return rc;
   KS_TRY(hipEventRecord(p->join, p->side));
-  if ((rc = keyswitch_on(p, pl, d, evk, out, b0, w, s, ha, hb)) != KS_OK) return rc;
+  if ((rc = keyswitch_on(p, pl, d, evk, out, b0, w, s, ev)) != KS_OK) return rc;
   KS_TRY(hipStreamWaitEvent(s, p->join, 0));
   return KS_OK;
 }
@@ -554,7 +553,7 @@ int ks_keyswitch(const ks_params* p, const uint64_t* d, const uint64_t* evk, uin
 
 // HMUL and HROT: element-wise pre-pass into the workspace, the KeySwitch of
 // one component straight into `out`, then the other part added to `out`
-// (HMUL under a fused plan folds the pre-pass and the add into the
+// (under a fused plan the pre-pass and the add are folded into the
 // KeySwitch's first and last passes instead).
 // Workspace: [t01: B*2*ell*N][d: B*ell*N][KeySwitch workspace].
 static size_t eval_extra(const ks_params* p, int batch) {
@@ -594,7 +593,7 @@ int ks_hmul(const ks_params* p, const uint64_t* a, const uint64_t* b, const uint
   uint64_t* d2 = t01 + (size_t)batch * 2 * LN;
   char* ksws = reinterpret_cast<char*>(ws) + eval_extra(p, batch);
   if (pl.dataflow != KS_STAGED)  // the tensor product fused into the KeySwitch's first and last passes
-    return keyswitch_any(p, pl, d2, evk, out, batch, ksws, s, a, b);
+    return keyswitch_any(p, pl, d2, evk, out, batch, ksws, s, ks::EvalIn{a, b, 0u});
   KS_TRY(traced(KS_K_EVAL, s, [&] { return ks::launch_tensor(p->tb, a, b, t01, d2, batch, s); }));
   if ((rc = keyswitch_any(p, pl, d2, evk, out, batch, ksws, s)) != KS_OK) return rc;
   KS_TRY(traced(KS_K_EVAL, s, [&] { return ks::launch_add_q(p->tb, out, t01, 2, batch, s); }));
@@ -616,6 +615,8 @@ int ks_hrot(const ks_params* p, const uint64_t* ct, int galois, const uint64_t* 
   uint64_t* t01 = reinterpret_cast<uint64_t*>(ws);  // sigma(c0) in component 0
   uint64_t* d = t01 + (size_t)batch * 2 * LN;        // sigma(c1)
   char* ksws = reinterpret_cast<char*>(ws) + eval_extra(p, batch);
+  if (pl.dataflow != KS_STAGED)  // sigma_g fused into the KeySwitch's first and last passes
+    return keyswitch_any(p, pl, d, evk, out, batch, ksws, s, ks::EvalIn{ct, nullptr, (uint32_t)galois});
   const int ell = p->hp.ell;
   KS_TRY(traced(KS_K_EVAL, s, [&] {
     return ks::launch_automorph(p->tb, ct, t01, ell, 2 * LN, 2 * LN, (uint32_t)galois, batch, s);

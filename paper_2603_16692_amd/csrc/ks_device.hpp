@@ -262,6 +262,23 @@ __device__ __forceinline__ void sub_inv(const Ar& A, typename Ar::T* x, uint32_t
   }
 }
 
+// Operands of HMUL or HROT folded into a fused KeySwitch (a == nullptr: a
+// plain KeySwitch). HMUL: ciphertexts a and b [items][2][ell][N], galois 0.
+// HROT: a the ciphertext to rotate, b unused, galois the Galois element.
+struct EvalIn {
+  const uint64_t* a;
+  const uint64_t* b;
+  uint32_t galois;
+};
+
+// Slot of the input that slot t of sigma_g(x) takes in NTT form (slot t holds
+// the evaluation at psi^(2 brv(t) + 1)): 2 brv(t') + 1 = g (2 brv(t) + 1) mod 2N.
+__device__ __forceinline__ uint32_t galois_src(uint32_t t, uint32_t g, int log_n) {
+  const uint32_t e = 2u * (__brev(t) >> (32 - log_n)) + 1u;
+  const uint32_t e2 = (uint32_t)(((uint64_t)g * e) & ((2u << log_n) - 1u));
+  return __brev((e2 - 1u) >> 1) >> (32 - log_n);
+}
+
 // LDS word of element x: one pad word after every 16, so that the strided
 // round layouts hit distinct banks.
 __device__ __forceinline__ int lds_pad(int x) { return x + (int)((unsigned)x >> 4); }

@@ -193,13 +193,14 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), LOGM >= 12 ? 4 : 1) void k_bl
   }
 }
 
-// HMUL's first pass: one block b of Q limb i of one item per workgroup
-// (placed by xcd_tile): d2 = a1 * b1 (canonical) into d2 [items][ell][N], and
-// its inverse block pass into t1 [items][ell][N], as k_blocks does for d.
-// a, b [items][2][ell][N] canonical.
+// The first pass of a fused HMUL or HROT (in place of the inverse block pass
+// of d): one block of one Q limb of one item per workgroup computes d = a1 b1
+// (HMUL) or d = sigma_g(c1) (HROT, a gather in NTT form), stores it (the
+// digit-parallel last pass reads it as its own digit) and runs the inverse
+// block pass into t1, as k_blocks<INV> does for d.
 template <int LOGM, int LOGE>
-__global__ __launch_bounds__((1 << (LOGM - LOGE)), LOGM >= 12 ? 4 : 1) void k_tensor_blocks(
-    DevTables tb, const uint64_t* a, const uint64_t* b, uint64_t* d2, uint64_t* t1, int items) {
+__global__ __launch_bounds__((1 << (LOGM - LOGE)), LOGM >= 12 ? 4 : 1) void k_eval_blocks(
+    DevTables tb, EvalIn ev, uint64_t* d2, uint64_t* t1, int items) {
   using B = BlockNtt<LOGM, LOGE>;
   extern __shared__ uint64_t lds[];
   const size_t N = (size_t)1 << tb.log_n;
@@ -209,14 +210,19 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), LOGM >= 12 ? 4 : 1) void k_te
   const int tid = threadIdx.x, blk = tl.tile % R, i = tl.tile / R;
   const LimbC L = tb.limb[i];
   const size_t boff = (size_t)blk * B::M;
-  const uint64_t* a1 = a + (((size_t)tl.item * 2 + 1) * ell + i) * N + boff;
-  const uint64_t* b1 = b + (((size_t)tl.item * 2 + 1) * ell + i) * N + boff;
+  const uint64_t* a1 = ev.a + (((size_t)tl.item * 2 + 1) * ell + i) * N;  // the limb's component 1
   const size_t off = ((size_t)tl.item * ell + i) * N + boff;
   double v[B::E];
 #pragma unroll
   for (int e = 0; e < B::E; ++e) {
     const int x = B::cl_pos(tid, e);
-    const uint64_t c = f_canon(f_mul(u2d(a1[x]), u2d(b1[x]), L.qd, L.qinv), L.qd, L.qinv);
+    uint64_t c;
+    if (ev.galois) {
+      c = a1[galois_src((uint32_t)(boff + x), ev.galois, tb.log_n)];
+    } else {
+      const uint64_t* b1 = ev.b + (((size_t)tl.item * 2 + 1) * ell + i) * N;
+      c = f_canon(f_mul(u2d(a1[boff + x]), u2d(b1[boff + x]), L.qd, L.qinv), L.qd, L.qinv);
+    }
     d2[off + x] = c;
     v[e] = u2d(c);
   }
@@ -225,11 +231,17 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), LOGM >= 12 ? 4 : 1) void k_te
   for (int e = 0; e < B::E; ++e) t1[off + B::fr_pos(tid, e)] = f_canon(v[e], L.qd, L.qinv);
 }
 
-// HMUL's tensor terms of one element, added to a ModDown output pair:
-// (o0, o1) += (a0 b0, a0 b1 + a1 b0), all reduced; r0 / r1 index component 0 / 1.
-__device__ __forceinline__ void add_tensor(const LimbC& L, const uint64_t* a, const uint64_t* b, size_t r0, size_t r1,
-                                           double& o0, double& o1) {
-  const double a0 = u2d(a[r0]), a1 = u2d(a[r1]), b0 = u2d(b[r0]), b1 = u2d(b[r1]);
+// The HMUL or HROT part of one output element pair of limb i, added to a
+// ModDown output (o0, o1) before its final reduction: (a0 b0, a0 b1 + a1 b0)
+// or (sigma_g(c0), 0). r0 / r1 index component 0 / 1 of the item's limb i,
+// slot t the element's slot in the limb.
+__device__ __forceinline__ void add_eval(const LimbC& L, const EvalIn& ev, size_t r0, size_t r1, uint32_t t,
+                                         int log_n, double& o0, double& o1) {
+  if (ev.galois) {
+    o0 += u2d(ev.a[r0 - t + galois_src(t, ev.galois, log_n)]);
+    return;
+  }
+  const double a0 = u2d(ev.a[r0]), a1 = u2d(ev.a[r1]), b0 = u2d(ev.b[r0]), b1 = u2d(ev.b[r1]);
   o0 += f_mul(a0, b0, L.qd, L.qinv);
   o1 += f_mul(a0, b1, L.qd, L.qinv) + f_mul(a1, b0, L.qd, L.qinv);
 }
@@ -810,7 +822,7 @@ template <int LOGM, int LOGE>
 __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_moddown_blocks(DevTables tb, const uint64_t* t2,
                                                                          const uint64_t* acc, uint64_t* out,
                                                                          int tgt0, int ntgt, int ics,
-                                                                         const uint64_t* ta, const uint64_t* tb2) {
+                                                                         EvalIn ev) {
   using B = BlockNtt<LOGM, LOGE>;
   extern __shared__ uint64_t lds[];
   const size_t N = (size_t)1 << tb.log_n;
@@ -838,12 +850,14 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_moddown_blocks(DevTabl
     const int x = B::cl_pos(tid, e);
     // |acc - v| <= 3.2q, |P^-1| <= q/2
     double w = f_mul(u2d(a[x]) - v[e], pinv, L.qd, L.qinv);
-    if (ta) {  // HMUL: this component's tensor term, a0 b0 or a0 b1 + a1 b0
-      const double a0 = u2d(ta[r0 + x]);
+    if (ev.a && ev.galois) {  // HROT: sigma_g(c0) in component 0
+      if (comp == 0) w += u2d(ev.a[r0 + galois_src((uint32_t)(boff + x), ev.galois, tb.log_n) - boff]);
+    } else if (ev.a) {  // HMUL: this component's tensor term, a0 b0 or a0 b1 + a1 b0
+      const double a0 = u2d(ev.a[r0 + x]);
       if (comp == 0)
-        w += f_mul(a0, u2d(tb2[r0 + x]), L.qd, L.qinv);
+        w += f_mul(a0, u2d(ev.b[r0 + x]), L.qd, L.qinv);
       else
-        w += f_mul(a0, u2d(tb2[r1 + x]), L.qd, L.qinv) + f_mul(u2d(ta[r1 + x]), u2d(tb2[r0 + x]), L.qd, L.qinv);
+        w += f_mul(a0, u2d(ev.b[r1 + x]), L.qd, L.qinv) + f_mul(u2d(ev.a[r1 + x]), u2d(ev.b[r0 + x]), L.qd, L.qinv);
     }
     o[x] = f_canon(w, L.qd, L.qinv);
   }
@@ -883,8 +897,7 @@ __device__ __forceinline__ void stage_twiddles(T* tw, const T* table, uint32_t B
 template <int LOGM, int LOGE>
 __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4 : 1) void k_moddown_km_blocks(
     DevTables tb, const uint64_t* d, const uint64_t* ext1, const uint64_t* evk, const uint64_t* t2, uint64_t* out,
-    int j0, int j1, int nslots, int slot_stride, int tgt0, int ntgt, int items, const uint64_t* ta,
-    const uint64_t* tb2) {
+    int j0, int j1, int nslots, int slot_stride, int tgt0, int ntgt, int items, EvalIn ev) {
   using B = BlockNtt<LOGM, LOGE>;
   extern __shared__ uint64_t lds[];
   double* ld = reinterpret_cast<double*>(lds);
@@ -989,7 +1002,7 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
     const int x = B::cl_pos(tid, e);
     double v0 = f_mul(f_red(s0[e], L.qd, L.qinv), pinv, L.qd, L.qinv);
     double v1 = f_mul(f_red(s1[e], L.qd, L.qinv), pinv, L.qd, L.qinv);
-    if (ta) add_tensor(L, ta, tb2, r0 + x, r1 + x, v0, v1);  // HMUL: |v| stays below 3q
+    if (ev.a) add_eval(L, ev, r0 + x, r1 + x, (uint32_t)(boff + x), tb.log_n, v0, v1);  // |v| stays below 3q
     out[r0 + x] = f_canon(v0, L.qd, L.qinv);
     out[r1 + x] = f_canon(v1, L.qd, L.qinv);
   }
@@ -1376,23 +1389,21 @@ struct ModdownColsMx {
 template <int LOGM, int LOGE>
 struct ModdownBlocks {
   static hipError_t run(const DevTables& tb, const uint64_t* t2, const uint64_t* acc, uint64_t* out, int tgt0,
-                        int tgt1, int items, const uint64_t* ta, const uint64_t* tb2, hipStream_t s) {
+                        int tgt1, int items, EvalIn ev, hipStream_t s) {
     using B = BlockNtt<LOGM, LOGE>;
     allow_lds<k_moddown_blocks<LOGM, LOGE>>();
     k_moddown_blocks<LOGM, LOGE><<<dim3(xcd_grid((tgt1 - tgt0) << (tb.log_n - LOGM), items * 2)), dim3(B::T),
-                                   block_lds<LOGM, LOGE>(), s>>>(tb, t2, acc, out, tgt0, tgt1 - tgt0, items * 2, ta,
-                                                                 tb2);
+                                   block_lds<LOGM, LOGE>(), s>>>(tb, t2, acc, out, tgt0, tgt1 - tgt0, items * 2, ev);
     return hipGetLastError();
   }
 };
 template <int LOGM, int LOGE>
-struct TensorBlocks {
-  static hipError_t run(const DevTables& tb, const uint64_t* a, const uint64_t* b, uint64_t* d2, uint64_t* t1,
-                        int items, hipStream_t s) {
+struct EvalBlocks {
+  static hipError_t run(const DevTables& tb, EvalIn ev, uint64_t* d2, uint64_t* t1, int items, hipStream_t s) {
     using B = BlockNtt<LOGM, LOGE>;
-    allow_lds<k_tensor_blocks<LOGM, LOGE>>();
-    k_tensor_blocks<LOGM, LOGE><<<dim3(xcd_grid(tb.ell << (tb.log_n - LOGM), items)), dim3(B::T),
-                                  block_lds<LOGM, LOGE>(), s>>>(tb, a, b, d2, t1, items);
+    allow_lds<k_eval_blocks<LOGM, LOGE>>();
+    k_eval_blocks<LOGM, LOGE><<<dim3(xcd_grid(tb.ell << (tb.log_n - LOGM), items)), dim3(B::T),
+                                block_lds<LOGM, LOGE>(), s>>>(tb, ev, d2, t1, items);
     return hipGetLastError();
   }
 };
@@ -1405,13 +1416,12 @@ template <int LOGM, int LOGE>
 struct ModdownKmBlocks {
   static hipError_t run(const DevTables& tb, const uint64_t* d, const uint64_t* ext1, const uint64_t* evk,
                         const uint64_t* t2, uint64_t* out, int j0, int j1, int nslots, int slot_stride, int tgt0,
-                        int tgt1, int items, const uint64_t* ta, const uint64_t* tb2, hipStream_t s) {
+                        int tgt1, int items, EvalIn ev, hipStream_t s) {
     using B = BlockNtt<LOGM, LOGE>;
     allow_lds<k_moddown_km_blocks<LOGM, LOGE>>();
     k_moddown_km_blocks<LOGM, LOGE><<<dim3(xcd_grid((tgt1 - tgt0) << (tb.log_n - LOGM), items)), dim3(B::T),
                                       km_lds<LOGM, LOGE>(), s>>>(tb, d, ext1, evk, t2, out, j0, j1, nslots,
-                                                                    slot_stride, tgt0, tgt1 - tgt0, items, ta,
-                                                                    tb2);
+                                                                    slot_stride, tgt0, tgt1 - tgt0, items, ev);
     return hipGetLastError();
   }
 };
@@ -1470,9 +1480,9 @@ hipError_t launch_intt_blocks(const DevTables& tb, int log_r, const uint64_t* sr
   return by_logm<BlocksInv>(tb.log_n - log_r, tb, src, dst, 0, nlimbs, items, 0, s);
 }
 
-hipError_t launch_tensor_blocks(const DevTables& tb, int log_r, const uint64_t* a, const uint64_t* b, uint64_t* d2,
-                                uint64_t* t1, int items, hipStream_t s) {
-  return by_logm<TensorBlocks>(tb.log_n - log_r, tb, a, b, d2, t1, items, s);
+hipError_t launch_eval_blocks(const DevTables& tb, int log_r, EvalIn ev, uint64_t* d2, uint64_t* t1, int items,
+                              hipStream_t s) {
+  return by_logm<EvalBlocks>(tb.log_n - log_r, tb, ev, d2, t1, items, s);
 }
 
 hipError_t launch_modup_cols(const DevTables& tb, int log_r, const uint64_t* t1, uint64_t* ext1, int j0, int nj,
@@ -1493,10 +1503,10 @@ hipError_t launch_keymult_blocks(const DevTables& tb, int log_r, const uint64_t*
 
 hipError_t launch_moddown_km_blocks(const DevTables& tb, int log_r, const uint64_t* d, const uint64_t* ext1,
                                     const uint64_t* evk, const uint64_t* t2, uint64_t* out, int j0, int j1,
-                                    int nslots, int slot_stride, int tgt0, int tgt1, int items, const uint64_t* ta,
-                                    const uint64_t* tb2, hipStream_t s) {
+                                    int nslots, int slot_stride, int tgt0, int tgt1, int items, EvalIn ev,
+                                    hipStream_t s) {
   return by_logm_k3<ModdownKmBlocks, true>(tb.log_n - log_r, tb, d, ext1, evk, t2, out, j0, j1, nslots, slot_stride, tgt0,
-                                     tgt1, items, ta, tb2, s);
+                                     tgt1, items, ev, s);
 }
 
 hipError_t launch_moddown_cols(const DevTables& tb, int log_r, const uint64_t* accp, uint64_t* t2, int tgt0,
@@ -1506,9 +1516,8 @@ hipError_t launch_moddown_cols(const DevTables& tb, int log_r, const uint64_t* a
 }
 
 hipError_t launch_moddown_blocks(const DevTables& tb, int log_r, const uint64_t* t2, const uint64_t* acc,
-                                 uint64_t* out, int tgt0, int tgt1, int items, const uint64_t* ta,
-                                 const uint64_t* tb2, hipStream_t s) {
-  return by_logm<ModdownBlocks>(tb.log_n - log_r, tb, t2, acc, out, tgt0, tgt1, items, ta, tb2, s);
+                                 uint64_t* out, int tgt0, int tgt1, int items, EvalIn ev, hipStream_t s) {
+  return by_logm<ModdownBlocks>(tb.log_n - log_r, tb, t2, acc, out, tgt0, tgt1, items, ev, s);
 }
 
 hipError_t launch_ext_blocks(const DevTables& tb, int log_r, uint64_t* ext, int items, hipStream_t s) {

@@ -34,17 +34,16 @@ hipError_t launch_keymult_blocks(const DevTables& tb, int log_r, const uint64_t*
 // ModDown's last block pass with the Q-limb KeyMult of digits [j0, j1) folded in.
 hipError_t launch_moddown_km_blocks(const DevTables& tb, int log_r, const uint64_t* d, const uint64_t* ext1,
                                     const uint64_t* evk, const uint64_t* t2, uint64_t* out, int j0, int j1,
-                                    int nslots, int slot_stride, int tgt0, int tgt1, int items, const uint64_t* ta,
-                                    const uint64_t* tb2, hipStream_t s);
+                                    int nslots, int slot_stride, int tgt0, int tgt1, int items, EvalIn ev,
+                                    hipStream_t s);
 hipError_t launch_moddown_cols(const DevTables& tb, int log_r, const uint64_t* accp, uint64_t* t2, int tgt0,
                                int tgt1, int items, int mfma, hipStream_t s);
-// ta, tb2 (HMUL, may be null): add the tensor terms of ciphertexts ta, tb2 [items][2][ell][N] to out.
+// ev (HMUL / HROT, ev.a null for a plain KeySwitch): adds the tensor terms or sigma_g(c0) to out.
 hipError_t launch_moddown_blocks(const DevTables& tb, int log_r, const uint64_t* t2, const uint64_t* acc,
-                                 uint64_t* out, int tgt0, int tgt1, int items, const uint64_t* ta,
-                                 const uint64_t* tb2, hipStream_t s);
-// HMUL's first pass: d2 = a1 b1 and its inverse block pass t1.
-hipError_t launch_tensor_blocks(const DevTables& tb, int log_r, const uint64_t* a, const uint64_t* b, uint64_t* d2,
-                                uint64_t* t1, int items, hipStream_t s);
+                                 uint64_t* out, int tgt0, int tgt1, int items, EvalIn ev, hipStream_t s);
+// First pass of a fused HMUL / HROT: d2 = a1 b1 or sigma_g(c1), and its inverse block pass t1.
+hipError_t launch_eval_blocks(const DevTables& tb, int log_r, EvalIn ev, uint64_t* d2, uint64_t* t1, int items,
+                              hipStream_t s);
 hipError_t launch_ext_blocks(const DevTables& tb, int log_r, uint64_t* ext, int items, hipStream_t s);
 hipError_t launch_pblocks_inv(const DevTables& tb, int log_r, const uint64_t* acc, uint64_t* accp, int items,
                               hipStream_t s);

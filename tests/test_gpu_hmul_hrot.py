@@ -52,13 +52,17 @@ def test_hmul_and_hrot_match_oracle(ks, dnum, log_n, ell, levels):
             out = empty(ref.shape)
             G.hmul(dev(a), dev(b), mk, out, batch, G.eval_workspace(batch, plan), plan)
             assert_same(host(out), ref, f"hmul level {level} {plan}")
-        for g in (5, 25, 2 * P.n - 1):
+        hrot_plans = (ks.make_plan(ks.DPOB, 1, 2, mfma=True), ks.make_plan(ks.DSOC, min(2, level), 3),
+                      ks.make_plan(ks.DPOC, min(2, level), 1, split=True), ks.make_plan(ks.STAGED))
+        for gi, g in enumerate((5, 25, 2 * P.n - 1)):
             rk_h = oracle.keygen_pair(Pt, oracle.automorph_coeffs(s, g), s)
             ref = oracle.hrot(P, a, g, rk_h, batch)
-            out = empty(ref.shape)
-            plan = ks.make_plan(ks.DPOB, 1, 2, mfma=True)
-            G.hrot(dev(a), g, dev(rk_h), out, batch, G.eval_workspace(batch, plan), plan)
-            assert_same(host(out), ref, f"hrot g={g} level {level}")
+            # sigma_g is folded into the KeySwitch's first and last passes
+            # under the fused plans, separate kernels under STAGED
+            for plan in (hrot_plans if gi == 0 else hrot_plans[:1]):
+                out = empty(ref.shape)
+                G.hrot(dev(a), g, dev(rk_h), out, batch, G.eval_workspace(batch, plan), plan)
+                assert_same(host(out), ref, f"hrot g={g} level {level} {plan}")
 
 
 def test_hrot_rejects_bad_galois_elements(ks):
