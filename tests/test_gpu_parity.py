@@ -311,3 +311,39 @@ def test_default_plan_valid_for_large_digits(ks):
     out = empty((1, 2, P.ell, P.n))
     G.keyswitch(dev(d), dev(evk), out, 1, G.workspace(1))
     assert_same(host(out), oracle.keyswitch(P, d, evk, 1), "alpha = 30")
+
+
+@pytest.mark.parametrize("dnum,log_n,ell,batch", [
+    (2, 10, 85, 1),   # ell + k = 128 limbs, the most the library takes; 43-prime digits
+    (6, 11, 6, 2),    # alpha = 1: every digit one prime, BConv an exact reduction
+    (1, 10, 12, 1),   # one digit holding every Q limb
+    (2, 3, 4, 3),     # N = 8, the smallest ring
+    (4, 12, 13, 2),   # ragged digits 4, 4, 4, 1
+])
+def test_extreme_shapes(ks, dnum, log_n, ell, batch):
+    G, P = params(ks, dnum, log_n, ell)
+    d = ciphertext_batch(P.q, P.n, batch)
+    _, _, evk = oracle.keygen(P, h=min(64, P.n // 2))
+    ref = oracle.keyswitch(P, d, evk, batch)
+    for plan in (None, ks.make_plan(ks.STAGED), ks.make_plan(ks.DSOB)):
+        out = empty(ref.shape)
+        G.keyswitch(dev(d), dev(evk), out, batch, G.workspace(batch, plan), plan)
+        assert_same(host(out), ref, f"{(dnum, log_n, ell)} {plan}")
+
+
+def test_limits_are_rejected_on_the_host(ks):
+    # checked before anything is enqueued: no kernel sees these sizes
+    for args in ((2, 10, 86), (1, 18, 4), (1, 2, 4), (5, 12, 4), (0, 12, 4)):
+        with pytest.raises(ks.KsError) as e:
+            ks.KsParams(*args)
+        assert e.value.code == ks.KS_EINVAL, args
+    G, P = params(ks, 2, 13, 6)
+    d = empty((1, P.ell, P.n))
+    out = empty((1, 2, P.ell, P.n))
+    evk = empty((P.ndig, 2, P.nl, P.n))
+    with pytest.raises(ks.KsError) as e:  # batch * max(2, ndig) above 65535 workgroup rows
+        G.keyswitch(d, evk, out, 40000, G.workspace(1))
+    assert e.value.code == ks.KS_EINVAL
+    with pytest.raises(ks.KsError) as e:
+        G.keyswitch(d, evk, out, -1, G.workspace(1))
+    assert e.value.code == ks.KS_EINVAL
