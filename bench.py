@@ -39,8 +39,8 @@ OP_METRIC = {"keyswitch": "KeySwitch/s", "hmul": "HMUL/s", "hrot": "HROT/s"}
 # (sha256 below) and for the same workload and plan; otherwise "traffic" is null.
 # The rocprofv3 summaries it comes from are under profiles/.
 TRAFFIC = {"workload": "c2", "plan": "Plan(DPOB, chunks=1, log_r=4, mfma)", "kernel": "moddown_blocks",
-           "fetch_kib": 467752.1, "fetch_scale": 2.0, "write_kib": 262144.0, "write_scale": 1.0,
-           "sources_sha256": "47cd2ebbc36d334886ce950fe5644026c2bcd911445ae54aef1a1da844c1838d"}
+           "fetch_kib": 467407.8, "fetch_scale": 2.0, "write_kib": 295831.6, "write_scale": 1.0,
+           "sources_sha256": "ddfbbf68423af4bc068d4da69daf1f0d62f541fde715e83080b14d5b649739d8"}
 TRAFFIC_SOURCES = ["paper_2603_16692_amd/csrc/ks_kernels.hip", "paper_2603_16692_amd/csrc/ks_device.hpp"]
 
 
