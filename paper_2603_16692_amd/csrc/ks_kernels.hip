@@ -213,18 +213,23 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), LOGM >= 12 ? 4 : 1) void k_ev
   const uint64_t* a1 = ev.a + (((size_t)tl.item * 2 + 1) * ell + i) * N;  // the limb's component 1
   const size_t off = ((size_t)tl.item * ell + i) * N + boff;
   double v[B::E];
+  if (ev.galois) {
 #pragma unroll
-  for (int e = 0; e < B::E; ++e) {
-    const int x = B::cl_pos(tid, e);
-    uint64_t c;
-    if (ev.galois) {
-      c = a1[galois_src((uint32_t)(boff + x), ev.galois, tb.log_n)];
-    } else {
-      const uint64_t* b1 = ev.b + (((size_t)tl.item * 2 + 1) * ell + i) * N;
-      c = f_canon(f_mul(u2d(a1[boff + x]), u2d(b1[boff + x]), L.qd, L.qinv), L.qd, L.qinv);
+    for (int e = 0; e < B::E; ++e) {
+      const int x = B::cl_pos(tid, e);
+      const uint64_t c = a1[galois_src((uint32_t)(boff + x), ev.galois, tb.log_n)];
+      d2[off + x] = c;
+      v[e] = u2d(c);
     }
-    d2[off + x] = c;
-    v[e] = u2d(c);
+  } else {
+    const uint64_t* b1 = ev.b + (((size_t)tl.item * 2 + 1) * ell + i) * N;
+#pragma unroll
+    for (int e = 0; e < B::E; ++e) {
+      const int x = B::cl_pos(tid, e);
+      const uint64_t c = f_canon(f_mul(u2d(a1[boff + x]), u2d(b1[boff + x]), L.qd, L.qinv), L.qd, L.qinv);
+      d2[off + x] = c;
+      v[e] = u2d(c);
+    }
   }
   B::inv(arf(tb, L, i, true), v, reinterpret_cast<double*>(lds), tid, (uint32_t)(R + blk));
 #pragma unroll
@@ -235,9 +240,10 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), LOGM >= 12 ? 4 : 1) void k_ev
 // ModDown output (o0, o1) before its final reduction: (a0 b0, a0 b1 + a1 b0)
 // or (sigma_g(c0), 0). r0 / r1 index component 0 / 1 of the item's limb i,
 // slot t the element's slot in the limb.
+template <bool HROT>
 __device__ __forceinline__ void add_eval(const LimbC& L, const EvalIn& ev, size_t r0, size_t r1, uint32_t t,
                                          int log_n, double& o0, double& o1) {
-  if (ev.galois) {
+  if constexpr (HROT) {
     o0 += u2d(ev.a[r0 - t + galois_src(t, ev.galois, log_n)]);
     return;
   }
@@ -845,22 +851,32 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_moddown_blocks(DevTabl
   const double pinv = tb.dn_pinv_d[i];
   const int item = ic >> 1, comp = ic & 1;
   const size_t r0 = ((size_t)item * 2 * tb.ell + i) * N + boff, r1 = r0 + (size_t)tb.ell * N;
+  // MODE 0: plain KeySwitch, 1: HMUL, 2: HROT (chosen once per workgroup)
+  auto finish = [&](auto mode) {
+    constexpr int MODE = decltype(mode)::value;
 #pragma unroll
-  for (int e = 0; e < B::E; ++e) {
-    const int x = B::cl_pos(tid, e);
-    // |acc - v| <= 3.2q, |P^-1| <= q/2
-    double w = f_mul(u2d(a[x]) - v[e], pinv, L.qd, L.qinv);
-    if (ev.a && ev.galois) {  // HROT: sigma_g(c0) in component 0
-      if (comp == 0) w += u2d(ev.a[r0 + galois_src((uint32_t)(boff + x), ev.galois, tb.log_n) - boff]);
-    } else if (ev.a) {  // HMUL: this component's tensor term, a0 b0 or a0 b1 + a1 b0
-      const double a0 = u2d(ev.a[r0 + x]);
-      if (comp == 0)
-        w += f_mul(a0, u2d(ev.b[r0 + x]), L.qd, L.qinv);
-      else
-        w += f_mul(a0, u2d(ev.b[r1 + x]), L.qd, L.qinv) + f_mul(u2d(ev.a[r1 + x]), u2d(ev.b[r0 + x]), L.qd, L.qinv);
+    for (int e = 0; e < B::E; ++e) {
+      const int x = B::cl_pos(tid, e);
+      // |acc - v| <= 3.2q, |P^-1| <= q/2
+      double w = f_mul(u2d(a[x]) - v[e], pinv, L.qd, L.qinv);
+      if constexpr (MODE == 2) {  // HROT: sigma_g(c0) in component 0
+        if (comp == 0) w += u2d(ev.a[r0 + galois_src((uint32_t)(boff + x), ev.galois, tb.log_n) - boff]);
+      } else if constexpr (MODE == 1) {  // HMUL: this component's tensor term, a0 b0 or a0 b1 + a1 b0
+        const double a0 = u2d(ev.a[r0 + x]);
+        if (comp == 0)
+          w += f_mul(a0, u2d(ev.b[r0 + x]), L.qd, L.qinv);
+        else
+          w += f_mul(a0, u2d(ev.b[r1 + x]), L.qd, L.qinv) + f_mul(u2d(ev.a[r1 + x]), u2d(ev.b[r0 + x]), L.qd, L.qinv);
+      }
+      o[x] = f_canon(w, L.qd, L.qinv);
     }
-    o[x] = f_canon(w, L.qd, L.qinv);
-  }
+  };
+  if (!ev.a)
+    finish(std::integral_constant<int, 0>{});
+  else if (!ev.galois)
+    finish(std::integral_constant<int, 1>{});
+  else
+    finish(std::integral_constant<int, 2>{});
 }
 
 // The twiddles one block pass reads, staged in LDS: entry x in [1, M) is
@@ -997,15 +1013,26 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
   }
   const double pinv = tb.dn_pinv_d[i];
   const size_t r0 = (((size_t)item * 2 + 0) * ell + i) * N + boff, r1 = (((size_t)item * 2 + 1) * ell + i) * N + boff;
+  // MODE 0: plain KeySwitch, 1: HMUL, 2: HROT (chosen once per workgroup)
+  auto finish = [&](auto mode) {
+    constexpr int MODE = decltype(mode)::value;
 #pragma unroll
-  for (int e = 0; e < B::E; ++e) {
-    const int x = B::cl_pos(tid, e);
-    double v0 = f_mul(f_red(s0[e], L.qd, L.qinv), pinv, L.qd, L.qinv);
-    double v1 = f_mul(f_red(s1[e], L.qd, L.qinv), pinv, L.qd, L.qinv);
-    if (ev.a) add_eval(L, ev, r0 + x, r1 + x, (uint32_t)(boff + x), tb.log_n, v0, v1);  // |v| stays below 3q
-    out[r0 + x] = f_canon(v0, L.qd, L.qinv);
-    out[r1 + x] = f_canon(v1, L.qd, L.qinv);
-  }
+    for (int e = 0; e < B::E; ++e) {
+      const int x = B::cl_pos(tid, e);
+      double v0 = f_mul(f_red(s0[e], L.qd, L.qinv), pinv, L.qd, L.qinv);
+      double v1 = f_mul(f_red(s1[e], L.qd, L.qinv), pinv, L.qd, L.qinv);
+      if constexpr (MODE != 0)  // |v| stays below 3q
+        add_eval<MODE == 2>(L, ev, r0 + x, r1 + x, (uint32_t)(boff + x), tb.log_n, v0, v1);
+      out[r0 + x] = f_canon(v0, L.qd, L.qinv);
+      out[r1 + x] = f_canon(v1, L.qd, L.qinv);
+    }
+  };
+  if (!ev.a)
+    finish(std::integral_constant<int, 0>{});
+  else if (!ev.galois)
+    finish(std::integral_constant<int, 1>{});
+  else
+    finish(std::integral_constant<int, 2>{});
 }
 
 // ------------------------------------------------------ standalone kernels
