@@ -414,7 +414,8 @@ __device__ __forceinline__ uint64_t mx_fold_p(double lo, double hi, const LimbC&
 // ([pairs][R][64] x 16 bytes) again, so that only one target's R values are
 // live: for each row the fold mod t, then the forward column pass and, if
 // `st`, the store of the R rows. Q groups store canonical residues, P groups
-// values in [0, 4p).
+// values in [0, 4p). The raised digits (and ModDown's t2) outgrow the caches,
+// so the stores are non-temporal (measured: 5% off the ModUp column kernel).
 template <int LOGR, bool QG, int NM, int PASS>
 __device__ __forceinline__ void mx_target(const DevTables& tb, const ulonglong2* yp, const ulonglong2 (&cst)[NM],
                                           int t0, int t1, bool st, uint64_t* o, size_t cc, int M) {
@@ -448,13 +449,13 @@ __device__ __forceinline__ void mx_target(const DevTables& tb, const ulonglong2*
     sub_fwd<LOGR>(ArF{q, qi, tb.twf_d + (size_t)t * N}, z, 1u);
     if (st) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) o[cc + (size_t)r * M] = f_canon(z[r], q, qi);
+      for (int r = 0; r < R; ++r) __builtin_nontemporal_store(f_canon(z[r], q, qi), o + cc + (size_t)r * M);
     }
   } else {
     sub_fwd<LOGR>(ArI{L.q, L.two_q, tb.twf + (size_t)t * N * 2}, z, 1u);
     if (st) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) o[cc + (size_t)r * M] = z[r];
+      for (int r = 0; r < R; ++r) __builtin_nontemporal_store(z[r], o + cc + (size_t)r * M);
     }
   }
 }
@@ -1023,8 +1024,8 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
       double v1 = f_mul(f_red(s1[e], L.qd, L.qinv), pinv, L.qd, L.qinv);
       if constexpr (MODE != 0)  // |v| stays below 3q
         add_eval<MODE == 2>(L, ev, r0 + x, r1 + x, (uint32_t)(boff + x), tb.log_n, v0, v1);
-      out[r0 + x] = f_canon(v0, L.qd, L.qinv);
-      out[r1 + x] = f_canon(v1, L.qd, L.qinv);
+      __builtin_nontemporal_store(f_canon(v0, L.qd, L.qinv), out + r0 + x);  // the result is not read again here
+      __builtin_nontemporal_store(f_canon(v1, L.qd, L.qinv), out + r1 + x);
     }
   };
   if (!ev.a)
