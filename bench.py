@@ -39,8 +39,8 @@ OP_METRIC = {"keyswitch": "KeySwitch/s", "hmul": "HMUL/s", "hrot": "HROT/s"}
 # (sha256 below) and for the same workload and plan; otherwise "traffic" is null.
 # The rocprofv3 summaries it comes from are under profiles/.
 TRAFFIC = {"workload": "c2", "plan": "Plan(DPOB, chunks=1, log_r=4, mfma)", "kernel": "moddown_blocks",
-           "fetch_kib": 467407.8, "fetch_scale": 2.0, "write_kib": 295831.6, "write_scale": 1.0,
-           "sources_sha256": "ddfbbf68423af4bc068d4da69daf1f0d62f541fde715e83080b14d5b649739d8"}
+           "fetch_kib": 467271.3, "fetch_scale": 2.0, "write_kib": 262170.4, "write_scale": 1.0,
+           "sources_sha256": "a8b527860c28fe6515b84d47bb3c846619e1f87fe2bd5eb7a6ddbdac478b315d"}
 TRAFFIC_SOURCES = ["paper_2603_16692_amd/csrc/ks_kernels.hip", "paper_2603_16692_amd/csrc/ks_device.hpp"]
 
 
