@@ -23,10 +23,10 @@ sys.path.insert(0, ROOT)
 
 # name: (dnum, log2 N, ell, batch, description)
 WORKLOADS = {
-    "c0": (2, 13, 6, 1, "plain KeySwitch (dnum,N,L)=(2,2^13,6)"),
-    "c1": (2, 15, 10, 32, "batched KeySwitch (dnum,N,L)=(2,2^15,10), batch 32, shared evk"),
-    "c2": (4, 16, 32, 8, "batched KeySwitch (dnum,N,L)=(4,2^16,32), batch 8, shared evk"),
-    "c3": (8, 17, 56, 2, "deep-circuit KeySwitch (dnum,N,L)=(8,2^17,56), batch 2"),
+    "d2-n13-l6": (2, 13, 6, 1, "plain KeySwitch (dnum,N,L)=(2,2^13,6)"),
+    "d2-n15-l10": (2, 15, 10, 32, "batched KeySwitch (dnum,N,L)=(2,2^15,10), batch 32, shared evk"),
+    "d4-n16-l32": (4, 16, 32, 8, "batched KeySwitch (dnum,N,L)=(4,2^16,32), batch 8, shared evk"),
+    "d8-n17-l56": (8, 17, 56, 2, "deep-circuit KeySwitch (dnum,N,L)=(8,2^17,56), batch 2"),
 }
 HBM_PEAK_GBS = 8000.0
 OP_METRIC = {"keyswitch": "KeySwitch/s", "hmul": "HMUL/s", "hrot": "HROT/s"}
@@ -38,7 +38,7 @@ OP_METRIC = {"keyswitch": "KeySwitch/s", "hmul": "HMUL/s", "hrot": "HROT/s"}
 # of them. The figure holds only for the kernel sources it was measured on
 # (sha256 below) and for the same workload and plan; otherwise "traffic" is null.
 # The rocprofv3 summaries it comes from are under profiles/.
-TRAFFIC = {"workload": "c2", "plan": "Plan(DPOB, chunks=1, log_r=4, mfma)", "kernel": "moddown_blocks",
+TRAFFIC = {"workload": "d4-n16-l32", "plan": "Plan(DPOB, chunks=1, log_r=4, mfma)", "kernel": "moddown_blocks",
            "fetch_kib": 467271.3, "fetch_scale": 2.0, "write_kib": 262170.4, "write_scale": 1.0,
            "sources_sha256": "a8b527860c28fe6515b84d47bb3c846619e1f87fe2bd5eb7a6ddbdac478b315d"}
 TRAFFIC_SOURCES = ["paper_2603_16692_amd/csrc/ks_kernels.hip", "paper_2603_16692_amd/csrc/ks_device.hpp"]
@@ -135,7 +135,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="d4-n16-l32", choices=sorted(WORKLOADS))
     ap.add_argument("--batch", type=int, default=0, help="override the workload's batch size")
     ap.add_argument("--op", default="keyswitch", choices=["keyswitch", "hmul", "hrot"],
                     help="the timed operation: KeySwitch, or HMUL / HROT around it (same plan)")

@@ -37,6 +37,12 @@
  *     synchronising; enqueued work may be captured into a HIP graph.
  *   - Errors: every int-returning call returns KS_OK (0) or a negative code;
  *     nothing is enqueued when a call fails. No exception crosses the ABI.
+ *   - Batch sizes: batch >= 0 (0 enqueues nothing); the items of a batch map
+ *     to one grid dimension of the column kernels, so batch * max(2, ndig)
+ *     <= 65535 for ks_keyswitch, ks_hmul and ks_hrot, batch * ndig <= 65535
+ *     for ks_modup, 2 * batch for ks_moddown, batch <= 65535 for ks_bconv
+ *     and ks_keymult (KS_EINVAL beyond). Larger batches are split by the
+ *     caller into several calls.
  */
 #ifndef KS_H
 #define KS_H

@@ -238,10 +238,10 @@ class GpuExecutor(Executor):
 # ------------------------------------------------------------------ benchmark
 
 SERVE_SETS = {  # name: (dnum, log2 N, L, batch limit, share of requests)
-    "c0": (2, 13, 6, 16, 0.4),
-    "c1": (2, 15, 10, 32, 0.3),
-    "c2": (4, 16, 32, 8, 0.2),
-    "c3": (8, 17, 56, 2, 0.1),
+    "d2-n13-l6": (2, 13, 6, 16, 0.4),
+    "d2-n15-l10": (2, 15, 10, 32, 0.3),
+    "d4-n16-l32": (4, 16, 32, 8, 0.2),
+    "d8-n17-l56": (8, 17, 56, 2, 0.1),
 }
 
 

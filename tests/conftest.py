@@ -15,10 +15,10 @@ def pytest_configure(config):
 
 # (dnum, log2 N, ell, batch) of the four benchmark parameter sets.
 CONFIGS = {
-    "c0": (2, 13, 6, 1),
-    "c1": (2, 15, 10, 32),
-    "c2": (4, 16, 32, 8),
-    "c3": (8, 17, 56, 2),
+    "d2-n13-l6": (2, 13, 6, 1),
+    "d2-n15-l10": (2, 15, 10, 32),
+    "d4-n16-l32": (4, 16, 32, 8),
+    "d8-n17-l56": (8, 17, 56, 2),
 }
 
 

@@ -153,7 +153,7 @@ def full_case(ks, name):
     return _full_cache[name]
 
 
-@pytest.mark.parametrize("name", ["c0", "c1", "c2", "c3"])
+@pytest.mark.parametrize("name", ["d2-n13-l6", "d2-n15-l10", "d4-n16-l32", "d8-n17-l56"])
 def test_keyswitch_benchmark_sizes(ks, name):
     G, P, s, s2, evk, d, ref, batch = full_case(ks, name)
     dd, ee = dev(d), dev(evk)

@@ -147,7 +147,7 @@ def test_keyswitch_decrypts_small(dnum, log_n, ell):
     assert not pins.decrypt_ok(P, d, out_bad, s, s2, h, 2)[0]
 
 
-@pytest.mark.parametrize("name", ["c0", "c1"])
+@pytest.mark.parametrize("name", ["d2-n13-l6", "d2-n15-l10"])
 def test_keyswitch_decrypts_benchmark_sizes(name):
     dnum, log_n, ell, _ = CONFIGS[name]
     P, s, s2, evk, d, out, ok, m = _decrypt_case(dnum, log_n, ell, 1)
@@ -156,7 +156,7 @@ def test_keyswitch_decrypts_benchmark_sizes(name):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("name", ["c2", "c3"])
+@pytest.mark.parametrize("name", ["d4-n16-l32", "d8-n17-l56"])
 def test_keyswitch_decrypts_large(name):
     dnum, log_n, ell, _ = CONFIGS[name]
     P, s, s2, evk, d, out, ok, m = _decrypt_case(dnum, log_n, ell, 1)
