@@ -39,8 +39,8 @@ OP_METRIC = {"keyswitch": "KeySwitch/s", "hmul": "HMUL/s", "hrot": "HROT/s"}
 # (sha256 below) and for the same workload and plan; otherwise "traffic" is null.
 # The rocprofv3 summaries it comes from are under profiles/.
 TRAFFIC = {"workload": "d4-n16-l32", "plan": "Plan(DPOB, chunks=1, log_r=4, mfma)", "kernel": "moddown_blocks",
-           "fetch_kib": 467271.3, "fetch_scale": 2.0, "write_kib": 262170.4, "write_scale": 1.0,
-           "sources_sha256": "a8b527860c28fe6515b84d47bb3c846619e1f87fe2bd5eb7a6ddbdac478b315d"}
+           "fetch_kib": 467280.6, "fetch_scale": 2.0, "write_kib": 262154.2, "write_scale": 1.0,
+           "sources_sha256": "dd078b0611658af0c463e3f65418ff57c13e1384102eaa681820ba8143068d74"}
 TRAFFIC_SOURCES = ["paper_2603_16692_amd/csrc/ks_kernels.hip", "paper_2603_16692_amd/csrc/ks_device.hpp"]
 
 
