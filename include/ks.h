@@ -80,6 +80,9 @@ typedef struct {
   int log_r;    /* NTT split N = 2^log_r * M: 2^log_r rows per column, blocks of M
                    coefficients (0 = one block pass, up to 5); negative = default */
   int flags;    /* KS_PLAN_MFMA_BCONV | KS_PLAN_SPLIT_STREAMS; other bits are rejected (KS_EUNSUP) */
+  int batch_tile; /* items per pass: 0 = the whole batch in one pass; else the batch runs in
+                     consecutive passes of at most batch_tile items in stream order, each reusing
+                     a workspace (and cache footprint) sized for one pass; negative = KS_EUNSUP */
 } ks_plan;
 
 /* Plan flag: run ModUp's and ModDown's fast base conversion (the BConv of

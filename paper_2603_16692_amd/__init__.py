@@ -33,16 +33,17 @@ PLAN_SPLIT_STREAMS = 2  # ks_plan.flags: the two halves of a batch on two stream
 
 class Plan(ctypes.Structure):
     _fields_ = [("dataflow", ctypes.c_int), ("chunks", ctypes.c_int), ("log_r", ctypes.c_int),
-                ("flags", ctypes.c_int)]
+                ("flags", ctypes.c_int), ("batch_tile", ctypes.c_int)]
 
     def __repr__(self):
         mx = ", mfma" if self.flags & PLAN_MFMA_BCONV else ""
         sp = ", split" if self.flags & PLAN_SPLIT_STREAMS else ""
+        tl = f", tile={self.batch_tile}" if self.batch_tile else ""
         return (f"Plan({DATAFLOW_NAMES.get(self.dataflow, self.dataflow)}, chunks={self.chunks}, "
-                f"log_r={self.log_r}{mx}{sp})")
+                f"log_r={self.log_r}{mx}{sp}{tl})")
 
     def key(self):
-        return (self.dataflow, self.chunks, self.log_r, self.flags)
+        return (self.dataflow, self.chunks, self.log_r, self.flags, self.batch_tile)
 
 
 class Info(ctypes.Structure):
@@ -121,11 +122,11 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def make_plan(dataflow=DPOB, chunks=1, log_r=-1, mfma=False, split=False):
+def make_plan(dataflow=DPOB, chunks=1, log_r=-1, mfma=False, split=False, tile=0):
     """A plan; log_r < 0 selects the library's default NTT split; mfma selects
     the int8 matrix-core BConv; split runs the two halves of a batch on two
-    streams."""
-    return Plan(dataflow, chunks, log_r, (PLAN_MFMA_BCONV if mfma else 0) | (PLAN_SPLIT_STREAMS if split else 0))
+    streams; tile > 0 runs the batch in passes of at most `tile` items."""
+    return Plan(dataflow, chunks, log_r, (PLAN_MFMA_BCONV if mfma else 0) | (PLAN_SPLIT_STREAMS if split else 0), tile)
 
 
 class KsParams:

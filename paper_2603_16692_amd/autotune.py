@@ -43,12 +43,16 @@ def footprint_bytes(dnum: int, n: int, ell: int, dataflow: int, chunks: int = 1,
     return f
 
 
-def candidate_plans(params, batch: int, chunk_range=CHUNK_RANGE, mfma=(False, True), split=None):
+def candidate_plans(params, batch: int, chunk_range=CHUNK_RANGE, mfma=(False, True), split=None, tiles=None):
     """Every plan libks accepts for these parameters and batch, with the
     FP64 / integer BConv and with the int8-MFMA BConv, and (batch >= 2) with
-    the batch on one stream or split over two."""
+    the batch on one stream or split over two; for batch >= 4 also the
+    digit-parallel plans (DPOB, STAGED) run in passes of batch/2 and batch/4
+    items, whose footprint is that of the smaller pass (the batch tile)."""
     if split is None:
         split = (False, True) if batch >= 2 else (False,)
+    if tiles is None:
+        tiles = sorted({batch // 2, batch // 4} - {0, 1}, reverse=True) if batch >= 4 else []
     plans = []
     for sp in split:
         for mx in mfma:
@@ -58,6 +62,8 @@ def candidate_plans(params, batch: int, chunk_range=CHUNK_RANGE, mfma=(False, Tr
                     continue
                 for df in (DSOB, DPOB, STAGED):
                     plans.append(make_plan(df, 1, log_r, mx, sp))
+                    if df != DSOB and not sp:
+                        plans += [make_plan(df, 1, log_r, mx, sp, t) for t in tiles]
                 for df in (DSOC, DPOC):
                     for c in chunk_range:
                         if c <= params.ell:
@@ -77,8 +83,9 @@ def prior_order(params, batch: int, plans, cache_bytes: int = MALL_BYTES):
     footprint stays within half of the cache comes first (the paper's 2x
     rule), then the others by how far their footprint is from that target."""
     def key(p):
+        per_pass = min(batch, p.batch_tile) if p.batch_tile else batch
         f = footprint_bytes(params.dnum, params.n, params.ell, p.dataflow if p.dataflow != STAGED else DPOB,
-                            p.chunks, batch)
+                            p.chunks, per_pass)
         fits = f * 2 <= cache_bytes
         launches = params.launch_count(batch, p)
         return (0 if fits else 1, launches if fits else f, p.log_r)
@@ -185,7 +192,8 @@ def cached_plan(params, batch: int, cache: dict):
         return None
     df, chunks, log_r = e["plan"][:3]
     flags = e["plan"][3] if len(e["plan"]) > 3 else 0
-    p = make_plan(df, chunks, log_r, bool(flags & PLAN_MFMA_BCONV), bool(flags & PLAN_SPLIT_STREAMS))
+    tile = e["plan"][4] if len(e["plan"]) > 4 else 0
+    p = make_plan(df, chunks, log_r, bool(flags & PLAN_MFMA_BCONV), bool(flags & PLAN_SPLIT_STREAMS), tile)
     try:
         params.workspace_bytes(batch, p)
     except KsError:

@@ -86,9 +86,10 @@ int resolve_plan(const ks_params* p, const ks_plan* in, ks_plan& out) {
   if (in) {
     out = *in;
   } else {
-    out = ks_plan{KS_DPOB, 1, -1, 0};
+    out = ks_plan{KS_DPOB, 1, -1, 0, 0};
   }
   if (out.flags & ~(KS_PLAN_MFMA_BCONV | KS_PLAN_SPLIT_STREAMS)) return KS_EUNSUP;
+  if (out.batch_tile < 0) return KS_EUNSUP;
   if (out.dataflow < KS_DSOB || out.dataflow > KS_STAGED) return KS_EUNSUP;
   if (out.log_r < 0) {
     // the default split, or the nearest smaller one whose column kernels can
@@ -158,8 +159,15 @@ bool split_batch(const ks_plan& plan, int batch, int& b0) {
   return (plan.flags & KS_PLAN_SPLIT_STREAMS) && batch >= 2;
 }
 
+// Items per pass: a tiled plan runs the batch in consecutive tiles of
+// batch_tile items, each with the workspace (and cache footprint) of a tile.
+int tile_of(const ks_plan& plan, int batch) {
+  return (plan.batch_tile > 0 && plan.batch_tile < batch) ? plan.batch_tile : batch;
+}
+
 size_t workspace_total(const ks_params* p, int batch, const ks_plan& plan) {
   int b0;
+  batch = tile_of(plan, batch);
   if (split_batch(plan, batch, b0)) return layout(p, b0, plan).total + layout(p, batch - b0, plan).total;
   return layout(p, batch, plan).total;
 }
@@ -414,12 +422,16 @@ int ks_launch_count(const ks_params* p, int batch, const ks_plan* plan) {
   const int rc = resolve_plan(p, plan, pl);
   if (rc != KS_OK) return rc;
   if (batch == 0) return 0;
-  int b0;
-  const int parts = split_batch(pl, batch, b0) ? 2 : 1;
-  if (pl.dataflow == KS_STAGED) return parts * (4 + 1 + 3);
   int n = 0;
   run_fused(p, pl, nullptr, nullptr, nullptr, batch, nullptr, nullptr, &n);
-  return parts * n;
+  const int per_pass = pl.dataflow == KS_STAGED ? 4 + 1 + 3 : n;
+  const int tile = tile_of(pl, batch);
+  int total = 0;
+  for (int t0 = 0; t0 < batch; t0 += tile) {
+    int b0;
+    total += (split_batch(pl, std::min(tile, batch - t0), b0) ? 2 : 1) * per_pass;
+  }
+  return total;
 }
 
 static int check_limbs(const ks_params* p, int first, int n_limbs, int batch) {
@@ -466,7 +478,7 @@ int ks_modup(const ks_params* p, const uint64_t* d, uint64_t* ext, int batch, vo
   int rc;
   if ((rc = check_ptr(d)) != KS_OK || (rc = check_ptr(ext)) != KS_OK || (rc = check_ptr(ws)) != KS_OK) return rc;
   ks_plan pl;
-  const ks_plan staged{KS_STAGED, 1, -1, 0};
+  const ks_plan staged{KS_STAGED, 1, -1, 0, 0};
   if ((rc = resolve_plan(p, &staged, pl)) != KS_OK) return rc;
   return run_modup(p, pl, d, ext, batch, reinterpret_cast<uint64_t*>(ws), (hipStream_t)stream);
 }
@@ -489,7 +501,7 @@ int ks_moddown(const ks_params* p, const uint64_t* acc, uint64_t* out, int batch
   int rc;
   if ((rc = check_ptr(acc)) != KS_OK || (rc = check_ptr(out)) != KS_OK || (rc = check_ptr(ws)) != KS_OK) return rc;
   ks_plan pl;
-  const ks_plan staged{KS_STAGED, 1, -1, 0};
+  const ks_plan staged{KS_STAGED, 1, -1, 0, 0};
   if ((rc = resolve_plan(p, &staged, pl)) != KS_OK) return rc;
   const size_t accp_bytes = up256((size_t)batch * 2 * p->hp.nl * p->hp.n * sizeof(uint64_t));
   uint64_t* accp = reinterpret_cast<uint64_t*>(ws);
@@ -515,8 +527,8 @@ static int keyswitch_on(const ks_params* p, const ks_plan& pl, const uint64_t* d
 }
 
 // keyswitch_on, or for a split plan its two halves on the two streams.
-static int keyswitch_any(const ks_params* p, const ks_plan& pl, const uint64_t* d, const uint64_t* evk,
-                         uint64_t* out, int batch, char* w, hipStream_t s, ks::EvalIn ev = ks::EvalIn{}) {
+static int keyswitch_pass(const ks_params* p, const ks_plan& pl, const uint64_t* d, const uint64_t* evk,
+                          uint64_t* out, int batch, char* w, hipStream_t s, ks::EvalIn ev) {
   int b0, rc;
   if (!split_batch(pl, batch, b0)) return keyswitch_on(p, pl, d, evk, out, batch, w, s, ev);
   // Items [b0, batch) on the second stream, after everything already on s;
@@ -534,6 +546,21 @@ static int keyswitch_any(const ks_params* p, const ks_plan& pl, const uint64_t* 
   KS_TRY(hipEventRecord(p->join, p->side));
   if ((rc = keyswitch_on(p, pl, d, evk, out, b0, w, s, ev)) != KS_OK) return rc;
   KS_TRY(hipStreamWaitEvent(s, p->join, 0));
+  return KS_OK;
+}
+
+// The batch in passes of batch_tile items (one pass without tiling), one
+// after another in stream order on s, each reusing the workspace.
+static int keyswitch_any(const ks_params* p, const ks_plan& pl, const uint64_t* d, const uint64_t* evk,
+                         uint64_t* out, int batch, char* w, hipStream_t s, ks::EvalIn ev = ks::EvalIn{}) {
+  const int tile = tile_of(pl, batch);
+  const size_t N = p->hp.n, ell = p->hp.ell;
+  for (int t0 = 0; t0 < batch; t0 += tile) {
+    const size_t ct = (size_t)t0 * 2 * ell * N;
+    const ks::EvalIn evt{ev.a ? ev.a + ct : nullptr, ev.b ? ev.b + ct : nullptr, ev.galois};
+    const int rc = keyswitch_pass(p, pl, d + (size_t)t0 * ell * N, evk, out + ct, std::min(tile, batch - t0), w, s, evt);
+    if (rc != KS_OK) return rc;
+  }
   return KS_OK;
 }
 

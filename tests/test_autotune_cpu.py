@@ -27,7 +27,8 @@ class FakeParams:
             raise ks.KsError(ks.KS_EUNSUP, "mfma")
         if plan.dataflow in (ks.DSOC, ks.DPOC) and not 1 <= plan.chunks <= min(64, self.ell):
             raise ks.KsError(ks.KS_EUNSUP, "chunks")
-        return batch * self.nl * self.n * 8
+        per_pass = min(batch, plan.batch_tile) if plan.batch_tile else batch
+        return per_pass * self.nl * self.n * 8
 
     def launch_count(self, batch, plan):
         return {ks.DPOB: 5, ks.STAGED: 8}.get(plan.dataflow, 5 * plan.chunks * self.ndig)
@@ -37,17 +38,21 @@ def test_candidates_cover_both_bconv_variants():
     P = FakeParams(4, 16, 32)
     plans = autotune.candidate_plans(P, 8)
     keys = {p.key() for p in plans}
-    assert (ks.DPOB, 1, 4, ks.PLAN_MFMA_BCONV) in keys and (ks.DPOB, 1, 4, 0) in keys
-    assert (ks.DPOB, 1, 5, 0) in keys and (ks.DPOB, 1, 5, ks.PLAN_MFMA_BCONV) in keys
+    assert (ks.DPOB, 1, 4, ks.PLAN_MFMA_BCONV, 0) in keys and (ks.DPOB, 1, 4, 0, 0) in keys
+    assert (ks.DPOB, 1, 5, 0, 0) in keys and (ks.DPOB, 1, 5, ks.PLAN_MFMA_BCONV, 0) in keys
     # 32 rows of 12-prime digits exceed the LDS of the MFMA BConv
     wide = {p.key() for p in autotune.candidate_plans(FakeParams(1, 12, 12), 1)}
-    assert (ks.DPOB, 1, 4, ks.PLAN_MFMA_BCONV) in wide and (ks.DPOB, 1, 5, ks.PLAN_MFMA_BCONV) not in wide
+    assert (ks.DPOB, 1, 4, ks.PLAN_MFMA_BCONV, 0) in wide and (ks.DPOB, 1, 5, ks.PLAN_MFMA_BCONV, 0) not in wide
     assert all(p.log_r >= 2 for p in plans)  # blocks of at most 2^14
     assert len(keys) == len(plans)
     # the batch split over two streams is a candidate only when there are two items
     split = ks.PLAN_SPLIT_STREAMS
-    assert (ks.DPOB, 1, 4, ks.PLAN_MFMA_BCONV | split) in keys
+    assert (ks.DPOB, 1, 4, ks.PLAN_MFMA_BCONV | split, 0) in keys
     assert not any(p.flags & split for p in autotune.candidate_plans(P, 1))
+    # batch tiles of B/2 and B/4 for the digit-parallel plans, none below a batch of 4
+    assert (ks.DPOB, 1, 4, ks.PLAN_MFMA_BCONV, 4) in keys and (ks.STAGED, 1, 4, 0, 2) in keys
+    assert not any(p.batch_tile and p.dataflow not in (ks.DPOB, ks.STAGED) for p in plans)
+    assert not any(p.batch_tile for p in autotune.candidate_plans(P, 3))
 
 
 def test_footprint_model_and_prior():
@@ -67,12 +72,15 @@ def test_table_lookup_exact_then_nearest_batch():
     P = FakeParams(4, 16, 32)
     key8 = autotune._cache_key(P, 8)
     table = {key8: {"plan": [ks.DPOB, 1, 4, ks.PLAN_MFMA_BCONV], "ms": 1.0, "name": "x"}}
-    assert autotune.cached_plan(P, 8, table).key() == (ks.DPOB, 1, 4, ks.PLAN_MFMA_BCONV)
+    assert autotune.cached_plan(P, 8, table).key() == (ks.DPOB, 1, 4, ks.PLAN_MFMA_BCONV, 0)
     assert autotune.cached_plan(P, 4, table) is None
-    assert autotune.plan_for(P, 4, table).key() == (ks.DPOB, 1, 4, ks.PLAN_MFMA_BCONV)
+    assert autotune.plan_for(P, 4, table).key() == (ks.DPOB, 1, 4, ks.PLAN_MFMA_BCONV, 0)
     # entries of three-field plans (no flags) still load
     table[autotune._cache_key(P, 2)] = {"plan": [ks.DSOC, 2, 3], "ms": 1.0, "name": "y"}
-    assert autotune.plan_for(P, 1, table).key() == (ks.DSOC, 2, 3, 0)
+    assert autotune.plan_for(P, 1, table).key() == (ks.DSOC, 2, 3, 0, 0)
+    # five-field entries carry the batch tile
+    table[autotune._cache_key(P, 32)] = {"plan": [ks.DPOB, 1, 4, 1, 8], "ms": 1.0, "name": "t"}
+    assert autotune.cached_plan(P, 32, table).batch_tile == 8
     # flags round-trip through the table
     table[autotune._cache_key(P, 16)] = {"plan": [ks.DPOB, 1, 4, 3], "ms": 1.0, "name": "w"}
     assert autotune.cached_plan(P, 16, table).flags == ks.PLAN_MFMA_BCONV | ks.PLAN_SPLIT_STREAMS

@@ -121,6 +121,11 @@ def _plans(ks, P, log_n):
             plans.append(ks.make_plan(df, chunks, log_r, mfma=True))  # the int8-MFMA BConv
             # the batch over two streams (3 items: 1 + 2)
             plans.append(ks.make_plan(df, chunks, log_r, mfma=True, split=True))
+            # passes of 2 + 1 items reusing one workspace, and of 1 item
+            plans.append(ks.make_plan(df, chunks, log_r, tile=2))
+            if log_r == 3:
+                plans.append(ks.make_plan(df, chunks, log_r, mfma=True, split=True, tile=2))
+                plans.append(ks.make_plan(df, chunks, log_r, tile=1))
     return plans
 
 
@@ -160,7 +165,7 @@ def test_keyswitch_benchmark_sizes(ks, name):
     plans = [None, ks.make_plan(ks.DSOB), ks.make_plan(ks.DPOC, 4), ks.make_plan(ks.DSOC, 2),
              ks.make_plan(ks.DPOB, 1, 4, mfma=True), ks.make_plan(ks.DSOC, 3, 3, mfma=True),
              ks.make_plan(ks.STAGED, 1, 4, mfma=True), ks.make_plan(ks.DPOB, 1, 4, mfma=True, split=True),
-             ks.make_plan(ks.DPOB, 1, 5, mfma=True)]
+             ks.make_plan(ks.DPOB, 1, 5, mfma=True), ks.make_plan(ks.DPOB, 1, 4, mfma=True, tile=3)]
     for plan in plans:
         out = empty(ref.shape)
         ws = G.workspace(batch, plan)
@@ -297,6 +302,14 @@ def test_launch_counts_follow_table_iii(ks):
     assert G.launch_count(4, sp) == 2 * G.launch_count(4, ks.make_plan(ks.DPOB))
     assert G.launch_count(1, sp) == G.launch_count(1, ks.make_plan(ks.DPOB))
     assert G.workspace_bytes(5, sp) == G.workspace_bytes(2) + G.workspace_bytes(3)
+    # a tiled batch runs one pass per tile in the workspace of one tile
+    tp = ks.make_plan(ks.DPOB, tile=3)
+    assert G.launch_count(8, tp) == 3 * G.launch_count(1, ks.make_plan(ks.DPOB))
+    assert G.workspace_bytes(8, tp) == G.workspace_bytes(3) < G.workspace_bytes(8)
+    assert G.launch_count(8, ks.make_plan(ks.DPOB, split=True, tile=3)) == 6 * 5
+    with pytest.raises(ks.KsError) as e:
+        G.workspace_bytes(8, ks.make_plan(ks.DPOB, tile=-1))
+    assert e.value.code == ks.KS_EUNSUP
 
 
 def test_default_plan_valid_for_large_digits(ks):
