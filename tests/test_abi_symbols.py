@@ -31,3 +31,17 @@ def test_binding_loads_and_lists_exports():
     assert set(k.EXPORTED) <= set(declared_symbols())
     assert k.raw_call("ks_strerror", 0) == b"ok"
     assert k.raw_call("ks_strerror", k.KS_EALIGN) == b"pointer not 256-byte aligned"
+
+
+def test_binding_structs_match_the_header():
+    # the ctypes mirrors of ks_plan and ks_info list the header's fields in order
+    import paper_2603_16692_amd as k
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "ks.h")).read(), flags=re.S)
+    structs = {name: body for body, name in re.findall(r"typedef struct \{([^{}]*)\}\s*(\w+);", text)}
+    for cname, pycls in (("ks_plan", k.Plan), ("ks_info", k.Info)):
+        fields = []
+        for decl in structs[cname].split(";"):
+            decl = decl.strip()
+            if decl:
+                fields += [re.sub(r"\[.*\]", "", n).strip() for n in decl.split(None, 1)[1].split(",")]
+        assert fields == [f[0] for f in pycls._fields_], (cname, fields)
