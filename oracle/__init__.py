@@ -65,6 +65,9 @@ def lib():
         L.orc_automorph.argtypes = [c_u64, c_u64, c_int, _u64p, c_u64, _u64p, c_int]
         L.orc_hmul_level.argtypes = [c_int, c_int, c_int, c_int, _u64p, _u64p, _u64p, _u64p, c_int]
         L.orc_hrot_level.argtypes = [c_int, c_int, c_int, c_int, _u64p, c_u64, _u64p, _u64p, c_int]
+        L.orc_sample_ternary.argtypes = [c_u64, ctypes.c_int64, c_int, _i8p]
+        L.orc_sample_gaussian.argtypes = [c_u64, ctypes.c_int64, ctypes.c_double, _i64p]
+        L.orc_key_sigma.restype = ctypes.c_double
         L.orc_max_threads.restype = c_int
         L.orc_set_threads.argtypes = [c_int]
         _lib = L
@@ -200,6 +203,28 @@ def keygen(P: Params, h: int = 64, seeds=(1, 2, 3, 4), noiseless: bool = False):
     if rc != 0:
         raise ValueError("keygen")
     return s, s2, evk
+
+
+def sample_ternary(seed: int, n: int, h: int) -> np.ndarray:
+    """The key generator's ternary secret: n coefficients, h of them nonzero."""
+    s = np.zeros(n, dtype=np.int8)
+    if lib().orc_sample_ternary(seed, n, h, s) != 0:
+        raise ValueError("sample_ternary")
+    return s
+
+
+def sample_gaussian(seed: int, count: int, sigma: float = None) -> np.ndarray:
+    """The key generator's rounded-Gaussian errors (sigma defaults to the
+    keys' own, key_sigma())."""
+    e = np.zeros(count, dtype=np.int64)
+    if lib().orc_sample_gaussian(seed, count, key_sigma() if sigma is None else float(sigma), e) != 0:
+        raise ValueError("sample_gaussian")
+    return e
+
+
+def key_sigma() -> float:
+    """Standard deviation of the evaluation-key errors."""
+    return float(lib().orc_key_sigma())
 
 
 def keygen_pair(P: Params, s_from, s_to, seeds=(3, 4), noiseless: bool = False) -> np.ndarray:

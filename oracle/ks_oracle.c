@@ -535,9 +535,15 @@ static void ternary(uint64_t seed, size_t n, int h, int8_t* s) {
   free(perm);
 }
 
-/* Rounded normal with sigma = 3.2 by Box-Muller, rejected beyond 6 sigma. */
-static void gaussian(uint64_t seed, size_t count, int64_t* e) {
-  const double sigma = 3.2, two_pi = 6.283185307179586;
+/* Standard deviation of the evaluation-key errors and the cut of their tail
+ * (|e| <= 19, i.e. about 6 sigma); the paper does not state a sampler. */
+#define ORC_SIGMA 3.2
+#define ORC_ERR_CUT 19.0
+
+/* Rounded normal with standard deviation sigma by Box-Muller, rejected
+ * beyond the cut. */
+static void gaussian(uint64_t seed, size_t count, double sigma, int64_t* e) {
+  const double two_pi = 6.283185307179586;
   uint64_t idx = 0;
   for (size_t i = 0; i < count; ++i) {
     for (;;) {
@@ -545,7 +551,7 @@ static void gaussian(uint64_t seed, size_t count, int64_t* e) {
       double u2 = (double)(splitmix64(seed, idx++) >> 11) * 0x1.0p-53;
       double z = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
       double v = nearbyint(sigma * z);
-      if (fabs(v) <= 19.0) { e[i] = (int64_t)v; break; }
+      if (fabs(v) <= ORC_ERR_CUT) { e[i] = (int64_t)v; break; }
     }
   }
 }
@@ -566,7 +572,7 @@ static void make_key(const orc_params* pp, const int64_t* s_from, const int64_t*
   size_t n = p.n;
   int nl = p.ell + p.k;
   int64_t* e = (int64_t*)calloc((size_t)p.ndig * n, sizeof(int64_t));
-  if (!noiseless) gaussian(seed_e, (size_t)p.ndig * n, e);
+  if (!noiseless) gaussian(seed_e, (size_t)p.ndig * n, ORC_SIGMA, e);
   for (int j = 0; j < p.ndig; ++j) {
     int lo = digit_lo(&p, j), hi = digit_hi(&p, j);
 #pragma omp parallel for schedule(static)
@@ -599,6 +605,24 @@ static void make_key(const orc_params* pp, const int64_t* s_from, const int64_t*
   }
   free(e);
 }
+
+/* The two samplers on their own, so that tests can check them against their
+ * definitions: a ternary secret of n coefficients with exactly h nonzeros,
+ * and `count` rounded-Gaussian errors of standard deviation sigma (the keys
+ * use ORC_SIGMA). */
+int orc_sample_ternary(uint64_t seed, int64_t n, int h, int8_t* s) {
+  if (n <= 0 || h < 0 || (int64_t)h > n) return -1;
+  ternary(seed, (size_t)n, h, s);
+  return 0;
+}
+
+int orc_sample_gaussian(uint64_t seed, int64_t count, double sigma, int64_t* e) {
+  if (count < 0 || !(sigma > 0.0)) return -1;
+  gaussian(seed, (size_t)count, sigma, e);
+  return 0;
+}
+
+double orc_key_sigma(void) { return ORC_SIGMA; }
 
 /* The key from s to s2 for two fresh ternary secrets with h nonzeros each
  * (seeds seed_s, seed_s2); s_out and s2_out receive them. */
