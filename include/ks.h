@@ -151,11 +151,20 @@ int ks_workspace_bytes(const ks_params* p, int batch, const ks_plan* plan, size_
 int ks_default_plan(const ks_params* p, int batch, ks_plan* plan);
 
 /* In-place forward / inverse NTT of x [batch][n_limbs][N]; limb r of each item
- * uses extended-basis prime basis_first + r. */
+ * uses extended-basis prime basis_first + r. The paper names the transform
+ * (Background section) but not its root or output order; the order here is
+ * the reading stated under "Transform" above (bit-reversed evaluation
+ * order, psi the smallest primitive 2N-th root), which every other call
+ * assumes for its NTT-form data. KS_EINVAL when the limb range leaves the
+ * extended basis. */
 int ks_ntt(const ks_params* p, uint64_t* x, int basis_first, int n_limbs, int batch, void* stream);
 int ks_intt(const ks_params* p, uint64_t* x, int basis_first, int n_limbs, int batch, void* stream);
 
-/* Fast base conversion in coefficient form. src_set = digit j: src
+/* Fast base conversion in coefficient form. The paper calls the conversion
+ * only approximately equivalent to the exact one; this library reads it as
+ * the fast conversion without overflow correction (stated under "BConv"
+ * above), whose result may exceed the exact one by u*S with
+ * 0 <= u < (number of source primes). src_set = digit j: src
  * [batch][|D_j|][N] over D_j -> dst [batch][ell+k-|D_j|][N] over the other limbs
  * of PQ in basis order. src_set = KS_SET_P: src [batch][k][N] over P -> dst
  * [batch][ell][N] over Q. */
@@ -197,7 +206,12 @@ int ks_hmul(const ks_params* p, const uint64_t* a, const uint64_t* b, const uint
  * `galois` (odd, 0 < galois < 2N; the automorphism x -> x^galois): for
  * ct = (c0, c1) [batch][2][ell][N],
  *   out = (sigma(c0), 0) + KeySwitch(sigma(c1)),
- * with evk the key from sigma(s) to s. In NTT form sigma permutes the slots:
+ * with evk the key from sigma(s) to s. This is a reading of the paper's
+ * formula, which puts the rotated second component in the first slot and
+ * key-switches the rotated first one: with the ciphertext convention of the
+ * paper's own HMUL (c0 + c1*s, the second component multiplying the
+ * secret), the component to key-switch is the one that multiplies
+ * sigma(s), i.e. sigma(c1), and sigma(c0) is kept as it is. In NTT form sigma permutes the slots:
  * slot t of the image is slot t' of the input with
  * 2 brv(t') + 1 = galois * (2 brv(t) + 1) mod 2N. A fused plan gathers
  * sigma(c1) in its first pass and adds sigma(c0) in its last; KS_STAGED runs

@@ -720,7 +720,12 @@ int orc_hmul_level(int dnum, int log_n, int ell, int level, const uint64_t* a, c
 
 /* HROT by the automorphism X -> X^g: out = (sigma(c0), 0) + KS(sigma(c1)),
  * the KeySwitch with the top-level key from sigma(s) to s.
- * ct, out [batch][2][level][N]. */
+ * ct, out [batch][2][level][N].
+ * This is a reading of the Background section's formula, which places the
+ * rotated second component first and key-switches the rotated first one:
+ * with the convention of the HMUL formula next to it (c0 + c1*s, so that
+ * the KS term there multiplies s^2), the component to switch is the one
+ * that multiplies sigma(s), sigma(c1). */
 int orc_hrot_level(int dnum, int log_n, int ell, int level, const uint64_t* ct, uint64_t g, const uint64_t* evk,
                    uint64_t* out, int batch) {
   orc_params p;
