@@ -41,8 +41,12 @@
  *     to one grid dimension of the column kernels, so batch * max(2, ndig)
  *     <= 65535 for ks_keyswitch, ks_hmul and ks_hrot, batch * ndig <= 65535
  *     for ks_modup, 2 * batch for ks_moddown, batch <= 65535 for ks_bconv
- *     and ks_keymult (KS_EINVAL beyond). Larger batches are split by the
- *     caller into several calls.
+ *     and ks_keymult, batch * n_limbs <= 65535 for ks_ntt and ks_intt; and
+ *     one call covers at most 2^31 coefficients per extended-basis array,
+ *     batch * (ell + k) * N <= 2^31 (batch * n_limbs * N for ks_ntt and
+ *     ks_intt), e.g. 260 items at (8, 2^17, 56). Every product is formed in
+ *     64 bits; KS_EINVAL beyond, before anything is enqueued. Larger batches
+ *     are split by the caller into several calls.
  */
 #ifndef KS_H
 #define KS_H

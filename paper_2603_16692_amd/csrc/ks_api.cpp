@@ -434,9 +434,22 @@ int ks_launch_count(const ks_params* p, int batch, const ks_plan* plan) {
   return total;
 }
 
+// The items of a batch times `per_item` grid rows must fit one 16-bit grid
+// dimension of the column kernels; the product is taken in 64 bits.
+static bool batch_fits(int batch, int per_item) {
+  return batch >= 0 && (int64_t)batch * (int64_t)per_item <= 65535;
+}
+
+// One call touches at most 2^31 coefficients per extended-basis array
+// (batch * (ell + k) * N), so that every flattened work-item index of its
+// launches fits in 31 bits.
+static bool coeffs_fit(const ks_params* p, int batch, int limbs) {
+  return (int64_t)batch * (int64_t)limbs * (int64_t)p->hp.n <= (int64_t(1) << 31);
+}
+
 static int check_limbs(const ks_params* p, int first, int n_limbs, int batch) {
   if (first < 0 || n_limbs < 0 || first + n_limbs > p->hp.nl || batch < 0) return KS_EINVAL;
-  if ((long)n_limbs * batch > 65535L * 65535L) return KS_EINVAL;
+  if (!batch_fits(batch, std::max(1, n_limbs)) || !coeffs_fit(p, batch, n_limbs)) return KS_EINVAL;
   return KS_OK;
 }
 
@@ -462,7 +475,7 @@ int ks_intt(const ks_params* p, uint64_t* x, int basis_first, int n_limbs, int b
 
 int ks_bconv(const ks_params* p, const uint64_t* src, int src_set, uint64_t* dst, int batch, void* stream) {
   if (!p) return KS_ENULL;
-  if (batch < 0 || batch > 65535) return KS_EINVAL;
+  if (!batch_fits(batch, 1) || !coeffs_fit(p, batch, p->hp.nl)) return KS_EINVAL;
   if (src_set != KS_SET_P && (src_set < 0 || src_set >= p->hp.ndig)) return KS_EINVAL;
   if (batch == 0) return KS_OK;
   int rc;
@@ -473,7 +486,7 @@ int ks_bconv(const ks_params* p, const uint64_t* src, int src_set, uint64_t* dst
 
 int ks_modup(const ks_params* p, const uint64_t* d, uint64_t* ext, int batch, void* ws, void* stream) {
   if (!p) return KS_ENULL;
-  if (batch < 0 || batch * p->hp.ndig > 65535) return KS_EINVAL;
+  if (!batch_fits(batch, p->hp.ndig) || !coeffs_fit(p, batch, p->hp.nl)) return KS_EINVAL;
   if (batch == 0) return KS_OK;
   int rc;
   if ((rc = check_ptr(d)) != KS_OK || (rc = check_ptr(ext)) != KS_OK || (rc = check_ptr(ws)) != KS_OK) return rc;
@@ -486,7 +499,7 @@ int ks_modup(const ks_params* p, const uint64_t* d, uint64_t* ext, int batch, vo
 int ks_keymult(const ks_params* p, const uint64_t* ext, const uint64_t* evk, uint64_t* acc, int batch,
                void* stream) {
   if (!p) return KS_ENULL;
-  if (batch < 0 || batch > 65535) return KS_EINVAL;
+  if (!batch_fits(batch, 1) || !coeffs_fit(p, batch, p->hp.nl)) return KS_EINVAL;
   if (batch == 0) return KS_OK;
   int rc;
   if ((rc = check_ptr(ext)) != KS_OK || (rc = check_ptr(evk)) != KS_OK || (rc = check_ptr(acc)) != KS_OK) return rc;
@@ -496,7 +509,7 @@ int ks_keymult(const ks_params* p, const uint64_t* ext, const uint64_t* evk, uin
 
 int ks_moddown(const ks_params* p, const uint64_t* acc, uint64_t* out, int batch, void* ws, void* stream) {
   if (!p) return KS_ENULL;
-  if (batch < 0 || batch * 2 > 65535) return KS_EINVAL;
+  if (!batch_fits(batch, 2) || !coeffs_fit(p, batch, p->hp.nl)) return KS_EINVAL;
   if (batch == 0) return KS_OK;
   int rc;
   if ((rc = check_ptr(acc)) != KS_OK || (rc = check_ptr(out)) != KS_OK || (rc = check_ptr(ws)) != KS_OK) return rc;
@@ -567,7 +580,7 @@ static int keyswitch_any(const ks_params* p, const ks_plan& pl, const uint64_t* 
 int ks_keyswitch(const ks_params* p, const uint64_t* d, const uint64_t* evk, uint64_t* out, int batch,
                  const ks_plan* plan, void* ws, void* stream) {
   if (!p) return KS_ENULL;
-  if (batch < 0 || batch * std::max(2, p->hp.ndig) > 65535) return KS_EINVAL;
+  if (!batch_fits(batch, std::max(2, p->hp.ndig)) || !coeffs_fit(p, batch, p->hp.nl)) return KS_EINVAL;
   ks_plan pl;
   int rc = resolve_plan(p, plan, pl);
   if (rc != KS_OK) return rc;
@@ -608,7 +621,7 @@ static int eval_check(const ks_params* p, const void* x, const void* y, const ui
 int ks_hmul(const ks_params* p, const uint64_t* a, const uint64_t* b, const uint64_t* evk, uint64_t* out, int batch,
             const ks_plan* plan, void* ws, void* stream) {
   if (!p) return KS_ENULL;
-  if (batch < 0 || batch * std::max(2, p->hp.ndig) > 65535) return KS_EINVAL;
+  if (!batch_fits(batch, std::max(2, p->hp.ndig)) || !coeffs_fit(p, batch, p->hp.nl)) return KS_EINVAL;
   ks_plan pl;
   int rc = resolve_plan(p, plan, pl);
   if (rc != KS_OK) return rc;
@@ -630,7 +643,7 @@ int ks_hmul(const ks_params* p, const uint64_t* a, const uint64_t* b, const uint
 int ks_hrot(const ks_params* p, const uint64_t* ct, int galois, const uint64_t* evk, uint64_t* out, int batch,
             const ks_plan* plan, void* ws, void* stream) {
   if (!p) return KS_ENULL;
-  if (batch < 0 || batch * std::max(2, p->hp.ndig) > 65535) return KS_EINVAL;
+  if (!batch_fits(batch, std::max(2, p->hp.ndig)) || !coeffs_fit(p, batch, p->hp.nl)) return KS_EINVAL;
   if (galois <= 0 || (galois & 1) == 0 || (size_t)galois >= 2 * p->hp.n) return KS_EINVAL;
   ks_plan pl;
   int rc = resolve_plan(p, plan, pl);

@@ -5,6 +5,8 @@ oracle's key generator; expected values come from the oracle only. Sizes
 span several workgroup tiles, odd limb counts and batch sizes, every NTT
 split, every dataflow, and the four benchmark parameter sets at full size.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -175,6 +177,29 @@ def test_keyswitch_benchmark_sizes(ks, name):
         del ws, out
     ok, m = pins.decrypt_ok(P, d, got, s, s2, 64, batch)
     assert ok, f"decryption error {m} above bound {oracle.ks_bound(P, 64)}"
+
+
+def test_keyswitch_deep_set_one_ciphertext(ks):
+    # (8, 2^17, 56) with one ciphertext at the top level, under the tuned
+    # plan of the shipped table, DSOB, the library default and two others;
+    # the oracle computes the items of a batch one by one, so the reference
+    # of item 0 is that of the batch case
+    from paper_2603_16692_amd import autotune
+    G, P, s, s2, evk, d, ref, _ = full_case(ks, "d8-n17-l56")
+    d1 = np.ascontiguousarray(d[:1])
+    ref1 = oracle.keyswitch(P, d1, evk, 1)
+    assert np.array_equal(ref1, ref[:1])
+    tuned = autotune.plan_for(G, 1, autotune.shipped_cache())
+    assert tuned is not None
+    dd, ee = dev(d1), dev(evk)
+    for plan in (tuned, ks.make_plan(ks.DSOB), None, ks.make_plan(ks.DSOB, 1, 5, mfma=True),
+                 ks.make_plan(ks.DPOC, 4, 4, mfma=True), ks.make_plan(ks.STAGED, 1, 5, mfma=True)):
+        out = empty(ref1.shape)
+        G.keyswitch(dd, ee, out, 1, G.workspace(1, plan), plan)
+        got = host(out)
+        assert_same(got, ref1, f"d8-n17-l56 batch 1 {plan}")
+    ok, m = pins.decrypt_ok(P, d1, got, s, s2, 64, 1)
+    assert ok, m
 
 
 def test_batch_item_equals_single(ks):
@@ -354,9 +379,31 @@ def test_limits_are_rejected_on_the_host(ks):
     d = empty((1, P.ell, P.n))
     out = empty((1, 2, P.ell, P.n))
     evk = empty((P.ndig, 2, P.nl, P.n))
-    with pytest.raises(ks.KsError) as e:  # batch * max(2, ndig) above 65535 workgroup rows
+    with pytest.raises(ValueError):  # the binding sees that the buffers hold one item
         G.keyswitch(d, evk, out, 40000, G.workspace(1))
-    assert e.value.code == ks.KS_EINVAL
     with pytest.raises(ks.KsError) as e:
         G.keyswitch(d, evk, out, -1, G.workspace(1))
     assert e.value.code == ks.KS_EINVAL
+    # straight through the C ABI, whose limits are checked before anything is
+    # enqueued: batch * max(2, ndig) above 65535 grid rows, products that wrap
+    # in 32 bits (2^30 * 2, 2^29 * 8), more than 2^31 coefficients per call
+    ws = G.workspace(1)
+    ptrs = [ctypes.c_void_p(t.data_ptr()) for t in (d, evk, out)]
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for batch in (40000, 1 << 29, 1 << 30, (1 << 31) - 1, -5):
+        rc = ks.raw_call("ks_keyswitch", G._h, *ptrs, batch, None, ctypes.c_void_p(ws.data_ptr()), stream)
+        assert rc == ks.KS_EINVAL, batch
+        rc = ks.raw_call("ks_hmul", G._h, ptrs[0], ptrs[0], ptrs[1], ptrs[2], batch, None,
+                         ctypes.c_void_p(ws.data_ptr()), stream)
+        assert rc == ks.KS_EINVAL, batch
+        rc = ks.raw_call("ks_modup", G._h, ptrs[0], ptrs[2], batch, ctypes.c_void_p(ws.data_ptr()), stream)
+        assert rc == ks.KS_EINVAL, batch
+        rc = ks.raw_call("ks_moddown", G._h, ptrs[2], ptrs[2], batch, ctypes.c_void_p(ws.data_ptr()), stream)
+        assert rc == ks.KS_EINVAL, batch
+        rc = ks.raw_call("ks_ntt", G._h, ptrs[0], 0, P.nl, batch, stream)
+        assert rc == ks.KS_EINVAL, batch
+    big, _ = params(ks, 8, 17, 56)
+    # (ell + k) * N = 63 * 2^17 coefficients per item: 261 items exceed 2^31 in one call
+    dummy = ctypes.c_void_p(ws.data_ptr())
+    assert ks.raw_call("ks_keyswitch", big._h, dummy, dummy, dummy, 261, None, dummy, stream) == ks.KS_EINVAL
+    torch.cuda.synchronize()
