@@ -107,6 +107,24 @@ def _check(rc, what):
         raise KsError(rc, what)
 
 
+def _need(t, words, what):
+    """Raise ValueError unless t is an int64 tensor of at least `words`
+    elements: the C ABI cannot see buffer sizes, so a short buffer would be
+    read or written past its end on the device."""
+    if t is None:
+        raise ValueError(f"{what}: missing tensor")
+    if t.dtype != torch.int64:
+        raise ValueError(f"{what}: expected dtype int64 (uint64 residues), got {t.dtype}")
+    if words > 0 and t.numel() < words:
+        raise ValueError(f"{what}: {t.numel()} elements, the call needs {words}")
+
+
+def _need_bytes(t, nbytes, what):
+    _need(t, 0, what)
+    if t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{what}: {t.numel() * t.element_size()} bytes, the call needs {nbytes}")
+
+
 def _ptr(t):
     if t is None:
         return None
@@ -188,30 +206,75 @@ class KsParams:
             raise KsError(rc, "ks_launch_count")
         return rc
 
+    # ---------------------------------------------- buffer-size checks
+    def _digit_size(self, j: int) -> int:
+        return min((j + 1) * self.alpha, self.ell) - j * self.alpha
+
+    def _key_words(self) -> int:
+        nd, two, rows, n = self.shapes(0)["evk"]
+        return nd * two * rows * n
+
+    def _staged_ws_bytes(self, batch: int) -> int:
+        return self.workspace_bytes(batch, make_plan(STAGED))
+
+    def check_keyswitch_args(self, d, evk, out, batch, ws, plan=None, eval_ws=False, d_words=None):
+        """ValueError unless every buffer of a KeySwitch-shaped call is int64
+        and large enough for `batch` items (d: batch*ell*N words, or d_words;
+        evk: the top-level key; out: batch*2*ell*N; ws: the workspace of the
+        plan)."""
+        if batch <= 0:
+            return
+        n, ell = self.n, self.ell
+        _need(d, batch * ell * n if d_words is None else d_words, "d")
+        _need(evk, self._key_words(), "evk")
+        _need(out, batch * 2 * ell * n, "out")
+        need = self.eval_workspace_bytes(batch, plan) if eval_ws else self.workspace_bytes(batch, plan)
+        _need_bytes(ws, need, "ws")
+
     # -------------------------------------------------------------- calls
     def ntt(self, x, basis_first=0, n_limbs=None, batch=None, stream=None):
         n_limbs = x.shape[-2] if n_limbs is None else n_limbs
         batch = (x.numel() // (n_limbs * self.n)) if batch is None else batch
+        _need(x, batch * n_limbs * self.n, "x")
         _check(_lib.ks_ntt(self._h, _ptr(x), basis_first, n_limbs, batch, _stream(stream)), "ks_ntt")
 
     def intt(self, x, basis_first=0, n_limbs=None, batch=None, stream=None):
         n_limbs = x.shape[-2] if n_limbs is None else n_limbs
         batch = (x.numel() // (n_limbs * self.n)) if batch is None else batch
+        _need(x, batch * n_limbs * self.n, "x")
         _check(_lib.ks_intt(self._h, _ptr(x), basis_first, n_limbs, batch, _stream(stream)), "ks_intt")
 
     def bconv(self, src, src_set, dst, batch, stream=None):
+        if batch > 0 and (src_set == KS_SET_P or 0 <= src_set < self.ndig):
+            ns = self.k if src_set == KS_SET_P else self._digit_size(src_set)
+            nd = self.ell if src_set == KS_SET_P else self.nl - ns
+            _need(src, batch * ns * self.n, "src")
+            _need(dst, batch * nd * self.n, "dst")
         _check(_lib.ks_bconv(self._h, _ptr(src), src_set, _ptr(dst), batch, _stream(stream)), "ks_bconv")
 
     def modup(self, d, ext, batch, ws, stream=None):
+        if batch > 0:
+            _need(d, batch * self.ell * self.n, "d")
+            _need(ext, batch * self.ndig * self.nl * self.n, "ext")
+            _need_bytes(ws, self._staged_ws_bytes(batch), "ws")
         _check(_lib.ks_modup(self._h, _ptr(d), _ptr(ext), batch, _ptr(ws), _stream(stream)), "ks_modup")
 
     def keymult(self, ext, evk, acc, batch, stream=None):
+        if batch > 0:
+            _need(ext, batch * self.ndig * self.nl * self.n, "ext")
+            _need(evk, self._key_words(), "evk")
+            _need(acc, batch * 2 * self.nl * self.n, "acc")
         _check(_lib.ks_keymult(self._h, _ptr(ext), _ptr(evk), _ptr(acc), batch, _stream(stream)), "ks_keymult")
 
     def moddown(self, acc, out, batch, ws, stream=None):
+        if batch > 0:
+            _need(acc, batch * 2 * self.nl * self.n, "acc")
+            _need(out, batch * 2 * self.ell * self.n, "out")
+            _need_bytes(ws, self._staged_ws_bytes(batch), "ws")
         _check(_lib.ks_moddown(self._h, _ptr(acc), _ptr(out), batch, _ptr(ws), _stream(stream)), "ks_moddown")
 
     def keyswitch(self, d, evk, out, batch, ws, plan: Plan = None, stream=None):
+        self.check_keyswitch_args(d, evk, out, batch, ws, plan)
         _check(_lib.ks_keyswitch(self._h, _ptr(d), _ptr(evk), _ptr(out), batch,
                                  ctypes.byref(plan) if plan else None, _ptr(ws), _stream(stream)), "ks_keyswitch")
 
@@ -227,11 +290,15 @@ class KsParams:
 
     def hmul(self, a, b, evk, out, batch, ws, plan: Plan = None, stream=None):
         """(a0 b0, a0 b1 + a1 b0) + KeySwitch(a1 b1); evk from s*s to s."""
+        self.check_keyswitch_args(a, evk, out, batch, ws, plan, eval_ws=True, d_words=batch * 2 * self.ell * self.n)
+        if batch > 0:
+            _need(b, batch * 2 * self.ell * self.n, "b")
         _check(_lib.ks_hmul(self._h, _ptr(a), _ptr(b), _ptr(evk), _ptr(out), batch,
                             ctypes.byref(plan) if plan else None, _ptr(ws), _stream(stream)), "ks_hmul")
 
     def hrot(self, ct, galois, evk, out, batch, ws, plan: Plan = None, stream=None):
         """(sigma(c0), 0) + KeySwitch(sigma(c1)) for x -> x^galois; evk from sigma(s) to s."""
+        self.check_keyswitch_args(ct, evk, out, batch, ws, plan, eval_ws=True, d_words=batch * 2 * self.ell * self.n)
         _check(_lib.ks_hrot(self._h, _ptr(ct), galois, _ptr(evk), _ptr(out), batch,
                             ctypes.byref(plan) if plan else None, _ptr(ws), _stream(stream)), "ks_hrot")
 
@@ -251,6 +318,7 @@ class Graph:
     """A captured KeySwitch (ks_graph_*); keeps its buffers alive while it lives."""
 
     def __init__(self, params, d, evk, out, batch, ws, plan=None, stream=None):
+        params.check_keyswitch_args(d, evk, out, batch, ws, plan)
         if stream is None:
             stream = torch.cuda.current_stream()
         if stream.cuda_stream == 0:
