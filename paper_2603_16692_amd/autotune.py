@@ -93,9 +93,14 @@ def prior_order(params, batch: int, plans, cache_bytes: int = MALL_BYTES):
 
 
 def _cache_key(params, batch: int) -> str:
+    """Device, ROCm version and the shape of the computation: dnum, N, the
+    Q limbs of the ciphertext (L, the level for a level handle) and the P
+    limbs k (= alpha, the digit size). A level handle keeps its top level's k,
+    so level 16 of (4, 2^16, 32) (k = 8, two digits) and a top-level
+    (4, 2^16, 16) set (k = 4, four digits) are different entries."""
     arch = torch.cuda.get_device_properties(0).gcnArchName if torch.cuda.is_available() else "cpu"
     rocm = getattr(torch.version, "hip", None) or "none"
-    return f"{arch}|rocm{rocm}|dnum{params.dnum}|logn{params.log_n}|L{params.ell}|B{batch}"
+    return f"{arch}|rocm{rocm}|dnum{params.dnum}|logn{params.log_n}|L{params.ell}|k{params.k}|B{batch}"
 
 
 SHIPPED_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_plans.json")

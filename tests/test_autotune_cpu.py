@@ -10,10 +10,10 @@ class FakeParams:
     chunks within ell, the MFMA BConv only up to 32 rows per column and
     16 sources, with its packed digits within the 160 KB of LDS."""
 
-    def __init__(self, dnum, log_n, ell):
+    def __init__(self, dnum, log_n, ell, top_ell=None):
         self.dnum, self.log_n, self.ell = dnum, log_n, ell
         self.n = 1 << log_n
-        self.alpha = -(-ell // dnum)
+        self.alpha = -(-(top_ell or ell) // dnum)
         self.k = self.alpha
         self.ndig = -(-ell // self.alpha)
         self.nl = ell + self.k
@@ -95,7 +95,24 @@ def test_shipped_table_entries_are_valid_plans():
     table = autotune.shipped_cache()
     assert table, "the package ships a tuning table"
     for key, e in table.items():
-        assert key.count("|") == 5 and e["ms"] > 0
+        assert key.count("|") == 6 and e["ms"] > 0
         f = e["plan"][3]
         p = ks.make_plan(*e["plan"][:3], bool(f & ks.PLAN_MFMA_BCONV), bool(f & ks.PLAN_SPLIT_STREAMS))
         assert p.dataflow in ks.DATAFLOW_NAMES
+
+
+def test_level_handles_and_top_level_sets_get_different_keys():
+    # level 16 of (4, 2^16, 32): alpha = k = 8, two digits; a top-level
+    # (4, 2^16, 16) set: alpha = k = 4, four digits; different computations
+    lvl = FakeParams(4, 16, 16, top_ell=32)
+    top = FakeParams(4, 16, 16)
+    assert (lvl.k, lvl.ndig) == (8, 2) and (top.k, top.ndig) == (4, 4)
+    assert autotune._cache_key(lvl, 8) != autotune._cache_key(top, 8)
+    table = {autotune._cache_key(lvl, 8): {"plan": [ks.DPOB, 1, 4, 1, 0], "ms": 1.0, "name": "lvl"}}
+    assert autotune.cached_plan(lvl, 8, table) is not None
+    assert autotune.cached_plan(top, 8, table) is None
+    assert autotune.plan_for(top, 8, table) is None  # no fallback across shapes either
+    # the shipped table has the per-level entries of (4, 2^16, 32) under k = 8
+    shipped = autotune.shipped_cache()
+    assert any("|dnum4|logn16|L16|k8|B8" in key for key in shipped)
+    assert not any("|dnum4|logn16|L16|k4|" in key for key in shipped)
