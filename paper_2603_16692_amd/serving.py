@@ -106,6 +106,8 @@ class Scheduler:
                 now = self.clock()
                 for r, res in zip(reqs, self.ex.finish(h)):
                     r.result, r.done = (res if self.keep_results else None), now
+                    if not self.keep_results:
+                        r.payload = None
                     self.completed.append(r)
                 self.in_use -= fp
                 finished += 1
@@ -145,7 +147,9 @@ class Scheduler:
         return self._poll() + self._admit()
 
     def run(self, requests: List[Request], offsets: List[float], idle_sleep: float = 0.0) -> List[Request]:
-        """Submit requests[i] at start + offsets[i] (seconds) and serve until all are done."""
+        """Submit requests[i] at start + offsets[i] (seconds) and serve until all are done.
+        With keep_results=False each request also drops its payload once it
+        completes."""
         order = sorted(range(len(requests)), key=lambda i: offsets[i])
         start = self.clock()
         nxt = 0
@@ -189,30 +193,38 @@ def latency_stats(done: List[Request]) -> Dict[str, float]:
 
 
 class GpuExecutor(Executor):
-    """libks on the current device: one torch stream per slot, resident keys."""
+    """libks on the current device: one torch stream per slot, resident keys,
+    and one workspace per (slot, set), allocated up front for the set's
+    largest batch and reused by every launch on that slot (a launch then
+    allocates only its stacked input and its output)."""
 
-    def __init__(self, sets: Dict[str, Any], evks: Dict[str, Any], plans: Dict[str, Any] = None, slots: int = 2):
+    def __init__(self, sets: Dict[str, Any], evks: Dict[str, Any], max_batch: Dict[str, int],
+                 plans: Dict[str, Any] = None, slots: int = 2):
         import torch
         self.torch = torch
         self.sets = sets            # name -> KsParams
         self.evks = evks            # name -> resident device key
         self.plans = plans or {}
+        self.max_batch = dict(max_batch)
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         self.free = list(range(slots))
-        self._ws = {}
+        self._ws = {(si, name): G.workspace(self.max_batch[name], self.plans.get(name))
+                    for si in range(slots) for name, G in sets.items()}
 
     def resident_bytes(self) -> int:
-        return sum(int(e.numel()) * 8 for e in self.evks.values())
+        keys = sum(int(e.numel()) * 8 for e in self.evks.values())
+        return keys + sum(int(w.numel()) * 8 for w in self._ws.values())
 
     def footprint(self, set_name: str, batch: int) -> int:
         G = self.sets[set_name]
-        data = batch * (G.ell + 2 * G.ell) * G.n * 8  # d batch + out
-        return data + G.workspace_bytes(batch, self.plans.get(set_name))
+        return batch * (G.ell + 2 * G.ell) * G.n * 8  # d batch + out (the workspace is resident)
 
     def launch(self, set_name: str, requests: List[Request]):
         torch = self.torch
         G = self.sets[set_name]
         b = len(requests)
+        if b > self.max_batch[set_name]:
+            raise ValueError(f"{set_name}: batch {b} above the executor's limit {self.max_batch[set_name]}")
         si = self.free.pop()
         st = self.streams[si]
         plan = self.plans.get(set_name)
@@ -220,19 +232,37 @@ class GpuExecutor(Executor):
         with torch.cuda.stream(st):
             d = torch.stack([r.payload for r in requests])
             out = torch.empty((b, 2, G.ell, G.n), dtype=torch.int64, device=d.device)
-            ws = G.workspace(b, plan)
-            G.keyswitch(d, self.evks[set_name], out, b, ws, plan, stream=st)
+            G.keyswitch(d, self.evks[set_name], out, b, self._ws[(si, set_name)], plan, stream=st)
             ev = torch.cuda.Event()
             ev.record(st)
-        return (ev, out, si, d, ws)
+        return (ev, out, si, d)
 
     def poll(self, handle) -> bool:
         return handle[0].query()
 
     def finish(self, handle) -> List[Any]:
-        ev, out, si, d, ws = handle
+        ev, out, si, d = handle
         self.free.append(si)
         return [out[i] for i in range(out.shape[0])]
+
+
+def uniform_q_residues(moduli, count: int, n: int, gen, device="cuda"):
+    """[count][len(moduli)][n] int64 residues, uniform modulo each modulus
+    (all below 2^50 and above 2^49), drawn on the device from the torch
+    generator `gen`: a 50-bit draw, replaced by a second 50-bit draw when it
+    is not below the modulus, and by a third draw reduced modulo the modulus
+    when that one is not either. Each modulus is within 2^-19 of 2^50 for the
+    parameter sets here, so the last case has probability below 2^-38 per
+    coefficient and the distribution is uniform up to that."""
+    import torch
+    if not all((1 << 49) < int(m) < (1 << 50) for m in moduli):
+        raise ValueError("moduli must lie in (2^49, 2^50)")
+    q = torch.tensor([int(m) for m in moduli], dtype=torch.int64, device=device)[None, :, None]
+    shape = (count, len(moduli), n)
+    r = torch.randint(0, 1 << 50, shape, generator=gen, device=device, dtype=torch.int64)
+    r2 = torch.randint(0, 1 << 50, shape, generator=gen, device=device, dtype=torch.int64)
+    r3 = torch.randint(0, 1 << 62, shape, generator=gen, device=device, dtype=torch.int64) % q
+    return torch.where(r < q, r, torch.where(r2 < q, r2, r3))
 
 
 # ------------------------------------------------------------------ benchmark
@@ -246,28 +276,39 @@ SERVE_SETS = {  # name: (dnum, log2 N, L, batch limit, share of requests)
 
 
 def serve_benchmark(n_requests: int = 4000, loads=(0.5, 0.8), slots: int = 2, budget_gb: float = 96.0,
-                    pool: int = 4, seed: int = 7) -> dict:
+                    seed: int = 7) -> dict:
     """The mixed-parameter serving stream: Poisson arrivals, requests drawn
-    40/30/20/10% from the four benchmark parameter sets with uniform random d
-    (from a pool of `pool` inputs per set), resident keys, admission by HBM
-    footprint, batching per set; against unbatched FIFO dispatch of the same
-    trace on one stream."""
+    40/30/20/10% from the four benchmark parameter sets, each with its own
+    uniform random d (drawn on the device before the run: about 10 MB per
+    request on average, 100 GB for 10 000 requests), resident keys, admission
+    by HBM footprint, batching per set; against unbatched FIFO dispatch of
+    the same trace on one stream. Both loads and both modes serve the same
+    requests."""
     import numpy as np
     import torch
 
     from . import KsParams
-    from synth import ciphertext_batch, uniform_key
+    from synth import uniform_key
 
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda")
-    sets, evks, payloads = {}, {}, {}
+    names = list(SERVE_SETS)
+    shares = {k: v[4] for k, v in SERVE_SETS.items()}
+    picks = choose_sets(n_requests, names, [shares[k] for k in names], seed=seed)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    sets, evks, payload = {}, {}, [None] * n_requests
     for name, (dn, ln, l, _, _) in SERVE_SETS.items():
         G = KsParams(dn, ln, l)
         sets[name] = G
         evks[name] = dev(uniform_key(G.moduli, G.n, G.ndig, seed=3))
-        payloads[name] = [dev(ciphertext_batch(G.moduli[:l], G.n, 1, seed_base=9000 + 31 * i)[0]) for i in range(pool)]
+        idx = [i for i in range(n_requests) if picks[i] == name]
+        for c0 in range(0, len(idx), 64):  # 64 requests per draw bound the temporaries
+            part = idx[c0:c0 + 64]
+            d = uniform_q_residues(G.moduli[:l], len(part), G.n, gen)
+            for j, i in enumerate(part):
+                payload[i] = d[j]
     torch.cuda.synchronize()
     max_batch = {k: v[3] for k, v in SERVE_SETS.items()}
-    shares = {k: v[4] for k, v in SERVE_SETS.items()}
     # per-set plans from the shipped tuning table (the library default where none fits)
     from . import autotune
     table = autotune.shipped_cache()
@@ -281,7 +322,7 @@ def serve_benchmark(n_requests: int = 4000, loads=(0.5, 0.8), slots: int = 2, bu
     rate = {}
     for name, G in sets.items():
         b = max_batch[name]
-        d = torch.stack([payloads[name][i % pool] for i in range(b)])
+        d = uniform_q_residues(G.moduli[:G.ell], b, G.n, gen)
         out = torch.empty((b, 2, G.ell, G.n), dtype=torch.int64, device="cuda")
         plan = plans.get(name)
         ws = G.workspace(b, plan)
@@ -295,18 +336,16 @@ def serve_benchmark(n_requests: int = 4000, loads=(0.5, 0.8), slots: int = 2, bu
         del d, out, ws
     capacity = 1.0 / sum(shares[k] / rate[k] for k in sets)
 
-    names = list(SERVE_SETS)
     result = {"capacity_req_per_s": round(capacity, 1), "set_rates_ks_per_s": {k: round(v, 1) for k, v in rate.items()},
               "plans": {k: repr(v) for k, v in plans.items()},
               "requests": n_requests, "slots": slots, "runs": []}
     for load in loads:
         lam = load * capacity
         offs = poisson_offsets(n_requests, lam, seed=seed)
-        picks = choose_sets(n_requests, names, [shares[k] for k in names], seed=seed)
         row = {"load": load, "rate_req_per_s": round(lam, 1)}
         for mode, mb, sl in (("batched", max_batch, slots), ("unbatched", {k: 1 for k in names}, 1)):
-            reqs = [Request(i, picks[i], payloads[picks[i]][i % pool]) for i in range(n_requests)]
-            ex = GpuExecutor(sets, evks, plans if mode == "batched" else {}, slots=sl)
+            reqs = [Request(i, picks[i], payload[i]) for i in range(n_requests)]
+            ex = GpuExecutor(sets, evks, mb, plans if mode == "batched" else {}, slots=sl)
             sched = Scheduler(ex, int(budget_gb * (1 << 30)), mb, slots=sl, keep_results=False)
             sched.run(reqs, offs)
             torch.cuda.synchronize()
@@ -314,6 +353,8 @@ def serve_benchmark(n_requests: int = 4000, loads=(0.5, 0.8), slots: int = 2, bu
             st["launches"] = sched.launches
             st["peak_hbm_gb"] = round(sched.peak_in_use / (1 << 30), 2)
             row[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+            del ex, sched, reqs
+            torch.cuda.empty_cache()
         result["runs"].append(row)
     return result
 

@@ -99,3 +99,39 @@ def test_hmul_hrot_decrypt_at_benchmark_size(ks):
     assert_same(got, oracle.hrot(P, a, g, rk, batch), "hrot")
     ok, m = pins.hrot_decrypt_ok(P, a, g, got, s, 64, batch)
     assert ok, m
+
+
+def test_hmul_hrot_headline_set_batch8(ks):
+    # (4, 2^16, 32), batch 8, under the shipped plan of this set (DPOB, log_r 4,
+    # int8-MFMA BConv) with the tensor product / automorphism fused, and
+    # under STAGED with them as kernels of their own
+    from paper_2603_16692_amd import autotune
+    dnum, log_n, ell, batch = 4, 16, 32, 8
+    G = ks.KsParams(dnum, log_n, ell)
+    P = oracle.Params(dnum, log_n, ell)
+    shipped = autotune.plan_for(G, batch, autotune.shipped_cache())
+    assert shipped is not None and shipped.key()[:4] == (ks.DPOB, 1, 4, ks.PLAN_MFMA_BCONV)
+    s, _, _ = oracle.keygen(P, h=64)
+    mk = oracle.keygen_pair(P, oracle.negacyclic_product(s, s), s)
+    a, b = _ct(P, batch, 41), _ct(P, batch, 42)
+    da, db, dk = dev(a), dev(b), dev(mk)
+    ref = oracle.hmul(P, a, b, mk, batch)
+    out = empty(ref.shape)
+    for plan in (shipped, ks.make_plan(ks.STAGED, 1, 4, mfma=True)):
+        out.zero_()
+        G.hmul(da, db, dk, out, batch, G.eval_workspace(batch, plan), plan)
+        got = host(out)
+        assert_same(got, ref, f"hmul (4, 2^16, 32) b8 {plan}")
+    ok, m = pins.hmul_decrypt_ok(P, a[:1], b[:1], got[:1], s, 64, 1)
+    assert ok, m
+    g = 5 ** 7 % (2 * P.n)
+    rk = oracle.keygen_pair(P, oracle.automorph_coeffs(s, g), s)
+    ref = oracle.hrot(P, a, g, rk, batch)
+    drk = dev(rk)
+    for plan in (shipped, ks.make_plan(ks.STAGED, 1, 4, mfma=True)):
+        out.zero_()
+        G.hrot(da, g, drk, out, batch, G.eval_workspace(batch, plan), plan)
+        got = host(out)
+        assert_same(got, ref, f"hrot (4, 2^16, 32) b8 {plan}")
+    ok, m = pins.hrot_decrypt_ok(P, a[:1], g, got[:1], s, 64, 1)
+    assert ok, m

@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import oracle
-from synth import ciphertext_batch
+from synth import ciphertext_batch, uniform_key
 
 from gpu_util import dev, empty, first_mismatch, host
 
@@ -82,24 +82,28 @@ def test_autotuner_keeps_only_bit_exact_plans(ks):
     assert first_mismatch(host(out), oracle.keyswitch(P, d, evk, batch)) is None
 
 
-def test_serving_results_equal_alone(ks):
+def _serve_and_check(ks, specs, weights, max_batch, n, rate, seed, oracle_checks, plans=None):
+    """Serve n requests of mixed sets through the continuous-batching loop;
+    every result must equal the KeySwitch of its request alone, and a few
+    must equal the oracle's."""
     from paper_2603_16692_amd.serving import GpuExecutor, Request, Scheduler, choose_sets, poisson_offsets
-    specs = {"small": (2, 13, 6), "mid": (2, 15, 10), "odd": (3, 12, 7)}
-    sets, evks, ps = {}, {}, {}
+    sets, evks, ps, hevk = {}, {}, {}, {}
     for name, (dn, ln, l) in specs.items():
         sets[name] = ks.KsParams(dn, ln, l)
         ps[name] = oracle.Params(dn, ln, l)
-        evks[name] = dev(oracle.keygen(ps[name], h=64)[2])
-    n = 60
-    names = choose_sets(n, list(specs), [0.4, 0.4, 0.2], seed=11)
-    offs = poisson_offsets(n, 4000.0, seed=11)
+        # the oracle's key for the small sets; a uniform key of the same shape for the large ones
+        hevk[name] = (oracle.keygen(ps[name], h=64)[2] if ln <= 15 else
+                      uniform_key(ps[name].moduli, ps[name].n, ps[name].ndig))
+        evks[name] = dev(hevk[name])
+    names = choose_sets(n, list(specs), weights, seed=seed)
+    offs = poisson_offsets(n, rate, seed=seed)
     reqs = []
     for i in range(n):
         P = ps[names[i]]
         reqs.append(Request(i, names[i], dev(ciphertext_batch(P.q, P.n, 1, seed_base=5000 + i)[0])))
     torch.cuda.synchronize()
-    ex = GpuExecutor(sets, evks, slots=2)
-    sched = Scheduler(ex, hbm_budget=8 << 30, max_batch={"small": 4, "mid": 8, "odd": 3}, slots=2)
+    ex = GpuExecutor(sets, evks, max_batch, plans, slots=2)
+    sched = Scheduler(ex, hbm_budget=64 << 30, max_batch=max_batch, slots=2)
     done = sched.run(reqs, offs)
     torch.cuda.synchronize()
     assert len(done) == n
@@ -109,9 +113,36 @@ def test_serving_results_equal_alone(ks):
         out = empty((1, 2, G.ell, G.n))
         G.keyswitch(r.payload[None].contiguous(), evks[r.set_name], out, 1, G.workspace(1))
         assert first_mismatch(host(r.result[None].contiguous()), host(out)) is None, f"request {r.rid}"
-    # a sample against the oracle
-    for r in done[:3]:
-        P = ps[r.set_name]
-        d = host(r.payload[None].contiguous())
-        ref = oracle.keyswitch(P, d, host(evks[r.set_name]).reshape(P.ndig, 2, P.nl, P.n), 1)
-        assert first_mismatch(host(r.result[None].contiguous()), ref) is None
+    checked = set()
+    for r in done:  # against the oracle: the first request of each named set
+        if r.set_name in oracle_checks and r.set_name not in checked:
+            checked.add(r.set_name)
+            P = ps[r.set_name]
+            d = host(r.payload[None].contiguous())
+            ref = oracle.keyswitch(P, d, hevk[r.set_name], 1)
+            assert first_mismatch(host(r.result[None].contiguous()), ref) is None, r.set_name
+    assert checked == set(oracle_checks)
+    return done
+
+
+def test_serving_results_equal_alone(ks):
+    specs = {"small": (2, 13, 6), "mid": (2, 15, 10), "odd": (3, 12, 7)}
+    _serve_and_check(ks, specs, [0.4, 0.4, 0.2], {"small": 4, "mid": 8, "odd": 3}, 60, 4000.0, 11,
+                     ("small", "mid", "odd"))
+
+
+def test_serving_mix_of_the_four_benchmark_sets(ks):
+    # the serving stream's mix: 40/30/20/10% of (2,2^13,6), (2,2^15,10),
+    # (4,2^16,32) and (8,2^17,56), each set under its shipped plan, batches of
+    # up to 16/32/8/2; results equal those of each request alone
+    from paper_2603_16692_amd import autotune
+    specs = {"d2-n13-l6": (2, 13, 6), "d2-n15-l10": (2, 15, 10), "d4-n16-l32": (4, 16, 32),
+             "d8-n17-l56": (8, 17, 56)}
+    max_batch = {"d2-n13-l6": 16, "d2-n15-l10": 32, "d4-n16-l32": 8, "d8-n17-l56": 2}
+    probe = {k: ks.KsParams(*v) for k, v in specs.items()}
+    plans = {k: autotune.plan_for(G, max_batch[k], autotune.shipped_cache()) for k, G in probe.items()}
+    del probe
+    done = _serve_and_check(ks, specs, [0.4, 0.3, 0.2, 0.1], max_batch, 80, 6000.0, 13,
+                            ("d2-n13-l6", "d4-n16-l32"), plans)
+    big = [r for r in done if r.set_name in ("d4-n16-l32", "d8-n17-l56")]
+    assert big and any(r.batch_size > 1 for r in big), "no large-set request was batched"
