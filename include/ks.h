@@ -268,6 +268,18 @@ void ks_graph_destroy(ks_graph* graph);
 int ks_trace_begin(void** events, int capacity, unsigned kind_mask);
 int ks_trace_end(int* kinds, int capacity);
 
+/* Throughput probe of the modular products the kernels are built from (the
+ * ALU roofline of the path): blocks x 256 threads each run ks_modmul_chains()
+ * independent chains of `iters` dependent products by a fixed residue, for
+ * kind 0 the FP64 product modulo the first Q prime (the Q-limb arithmetic),
+ * 1 the Shoup product and 2 the Montgomery product modulo the first P prime
+ * (the P-limb arithmetic); each thread writes one word of its result to
+ * sink [blocks * 256] (a device buffer the caller owns). Time it with events
+ * on `stream`: products = blocks * 256 * ks_modmul_chains() * iters.
+ * KS_EINVAL for another kind, blocks outside [1, 2^20] or iters < 1. */
+int ks_modmul_rate(const ks_params* p, int kind, int blocks, int iters, uint64_t* sink, void* stream);
+int ks_modmul_chains(void);
+
 const char* ks_strerror(int code);
 /* Name of the HIP error behind the calling thread's last KS_EHIP. */
 const char* ks_last_hip_error(void);

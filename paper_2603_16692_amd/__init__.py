@@ -71,6 +71,8 @@ _lib.ks_hmul.argtypes = [_vp, _vp, _vp, _vp, _vp, _i, ctypes.POINTER(Plan), _vp,
 _lib.ks_hrot.argtypes = [_vp, _vp, _i, _vp, _vp, _i, ctypes.POINTER(Plan), _vp, _vp]
 _lib.ks_eval_workspace_bytes.argtypes = [_vp, _i, ctypes.POINTER(Plan), ctypes.POINTER(_sz)]
 _lib.ks_launch_count.argtypes = [_vp, _i, ctypes.POINTER(Plan)]
+_lib.ks_modmul_rate.argtypes = [_vp, _i, _i, _i, _vp, _vp]
+_lib.ks_modmul_chains.restype = _i
 _lib.ks_strerror.argtypes = [_i]
 _lib.ks_strerror.restype = ctypes.c_char_p
 _lib.ks_last_hip_error.restype = ctypes.c_char_p
@@ -90,7 +92,7 @@ EXPORTED = ["ks_params_create", "ks_params_destroy", "ks_params_at_level", "ks_p
             "ks_default_plan", "ks_hmul", "ks_hrot", "ks_eval_workspace_bytes",
             "ks_ntt", "ks_intt", "ks_bconv", "ks_modup", "ks_keymult", "ks_moddown", "ks_keyswitch",
             "ks_launch_count", "ks_strerror", "ks_last_hip_error", "ks_trace_begin", "ks_trace_end",
-            "ks_graph_create", "ks_graph_launch", "ks_graph_destroy"]
+            "ks_graph_create", "ks_graph_launch", "ks_graph_destroy", "ks_modmul_rate", "ks_modmul_chains"]
 
 
 class KsError(RuntimeError):
@@ -301,6 +303,22 @@ class KsParams:
         self.check_keyswitch_args(ct, evk, out, batch, ws, plan, eval_ws=True, d_words=batch * 2 * self.ell * self.n)
         _check(_lib.ks_hrot(self._h, _ptr(ct), galois, _ptr(evk), _ptr(out), batch,
                             ctypes.byref(plan) if plan else None, _ptr(ws), _stream(stream)), "ks_hrot")
+
+    def modmul_rate(self, kind: int, blocks: int = 4096, iters: int = 2048, reps: int = 3) -> float:
+        """Measured modular products per second of one kind (0 FP64, 1 Shoup,
+        2 Montgomery; ks_modmul_rate), the best of `reps` timed launches."""
+        sink = torch.empty(blocks * 256, dtype=torch.int64, device="cuda")
+        stream = torch.cuda.current_stream()
+        ev = HipEvents(2)
+        _check(_lib.ks_modmul_rate(self._h, kind, blocks, iters, _ptr(sink), _stream(stream)), "ks_modmul_rate")
+        best = float("inf")
+        for _ in range(reps):
+            ev.record(0, stream)
+            _check(_lib.ks_modmul_rate(self._h, kind, blocks, iters, _ptr(sink), _stream(stream)), "ks_modmul_rate")
+            ev.record(1, stream)
+            torch.cuda.synchronize()
+            best = min(best, ev.elapsed_ms(0, 1))
+        return blocks * 256 * _lib.ks_modmul_chains() * iters / (best / 1e3)
 
     def graph(self, d, evk, out, batch, ws, plan: Plan = None, stream=None) -> "Graph":
         """Capture one KeySwitch on these buffers into a replayable HIP graph."""

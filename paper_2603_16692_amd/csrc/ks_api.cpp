@@ -669,6 +669,21 @@ int ks_hrot(const ks_params* p, const uint64_t* ct, int galois, const uint64_t* 
   return KS_OK;
 }
 
+int ks_modmul_rate(const ks_params* p, int kind, int blocks, int iters, uint64_t* sink, void* stream) {
+  if (!p) return KS_ENULL;
+  if (kind < 0 || kind > 2 || blocks < 1 || blocks > (1 << 20) || iters < 1) return KS_EINVAL;
+  int rc;
+  if ((rc = check_ptr(sink)) != KS_OK) return rc;
+  // the FP64 product on the first Q prime, the integer products on the first P prime
+  const uint64_t q = p->hp.mod[kind == 0 ? 0 : p->hp.ell];
+  const uint64_t w = q / 3 + 1;
+  KS_TRY(ks::launch_modmul_rate(kind, blocks, iters, q, w, ks::host_shoup(w, q), ks::host_mont_neg_inv(q), sink,
+                                (hipStream_t)stream));
+  return KS_OK;
+}
+
+int ks_modmul_chains(void) { return ks::MODMUL_CHAINS; }
+
 const char* ks_strerror(int code) {
   switch (code) {
     case KS_OK: return "ok";

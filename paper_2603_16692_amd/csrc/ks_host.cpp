@@ -144,6 +144,9 @@ void mx_lane(uint64_t* out, int l, int m, int nsrc, Cst cst) {
 
 }  // namespace
 
+uint64_t host_shoup(uint64_t w, uint64_t q) { return shoup(w, q); }
+uint64_t host_mont_neg_inv(uint64_t q) { return mont_neg_inv(q); }
+
 bool derive_params(int dnum, int log_n, int ell, HostParams& hp) {
   if (log_n < 3 || log_n > 17 || ell < 1 || dnum < 1 || dnum > ell) return false;
   hp = HostParams{};

@@ -31,5 +31,7 @@ void build_tables(const HostParams& hp, std::vector<uint64_t>& blob, DevTables& 
 
 uint64_t host_mulmod(uint64_t a, uint64_t b, uint64_t m);
 uint64_t host_powmod(uint64_t a, uint64_t e, uint64_t m);
+uint64_t host_shoup(uint64_t w, uint64_t q);       // floor(w * 2^64 / q)
+uint64_t host_mont_neg_inv(uint64_t q);            // -q^-1 mod 2^64
 
 }  // namespace ks

@@ -1602,6 +1602,59 @@ hipError_t launch_add_q(const DevTables& tb, uint64_t* out, const uint64_t* add,
   return hipGetLastError();
 }
 
+// Throughput probe of the three modular products the kernels are built
+// from. Every thread runs MM_CHAINS independent chains of `iters` dependent
+// products by a fixed operand (enough chains to hide the latency of one
+// product), then folds its chains into sink[thread] so that no product is
+// dead code. kind 0: FP64 product of the Q primes (f_mul); 1: Shoup product
+// of the P primes (mul_shoup); 2: Montgomery product (mont_mul).
+constexpr int MM_CHAINS = MODMUL_CHAINS;
+
+template <int KIND>
+__global__ __launch_bounds__(256) void k_modmul_rate(int iters, uint64_t q, uint64_t w, uint64_t ws, uint64_t ninv,
+                                                     double qd, double qinv, double wd, uint64_t* sink) {
+  const uint32_t tid = blockIdx.x * 256u + threadIdx.x;
+  if (KIND == 0) {
+    double a[MM_CHAINS];
+#pragma unroll
+    for (int c = 0; c < MM_CHAINS; ++c) a[c] = (double)(tid * MM_CHAINS + c + 1);
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+      for (int c = 0; c < MM_CHAINS; ++c) a[c] = f_mul(a[c], wd, qd, qinv);
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < MM_CHAINS; ++c) acc = f_red(acc + a[c], qd, qinv);
+    sink[tid] = f_canon(acc, qd, qinv);
+  } else {
+    uint64_t a[MM_CHAINS];
+#pragma unroll
+    for (int c = 0; c < MM_CHAINS; ++c) a[c] = (uint64_t)(tid * MM_CHAINS + c + 1);
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+      for (int c = 0; c < MM_CHAINS; ++c) a[c] = KIND == 1 ? mul_shoup(a[c], w, ws, q) : mont_mul(a[c], w, q, ninv);
+    }
+    uint64_t acc = 0;
+#pragma unroll
+    for (int c = 0; c < MM_CHAINS; ++c) acc ^= a[c];
+    sink[tid] = acc;
+  }
+}
+
+hipError_t launch_modmul_rate(int kind, int blocks, int iters, uint64_t q, uint64_t w, uint64_t ws, uint64_t ninv,
+                              uint64_t* sink, hipStream_t s) {
+  const double qd = (double)q, qinv = 1.0 / qd;
+  // the fixed operand in balanced form for the FP64 product
+  const double wd = w > q / 2 ? (double)w - qd : (double)w;
+  switch (kind) {
+    case 0: k_modmul_rate<0><<<dim3(blocks), dim3(256), 0, s>>>(iters, q, w, ws, ninv, qd, qinv, wd, sink); break;
+    case 1: k_modmul_rate<1><<<dim3(blocks), dim3(256), 0, s>>>(iters, q, w, ws, ninv, qd, qinv, wd, sink); break;
+    case 2: k_modmul_rate<2><<<dim3(blocks), dim3(256), 0, s>>>(iters, q, w, ws, ninv, qd, qinv, wd, sink); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_keymult(const DevTables& tb, const uint64_t* ext, const uint64_t* evk, uint64_t* acc, int items,
                           hipStream_t s) {
   const unsigned n = 1u << tb.log_n;

@@ -60,5 +60,11 @@ hipError_t launch_add_q(const DevTables& tb, uint64_t* out, const uint64_t* add,
                         hipStream_t s);
 hipError_t launch_keymult(const DevTables& tb, const uint64_t* ext, const uint64_t* evk, uint64_t* acc, int items,
                           hipStream_t s);
+// Modular-product throughput probe: blocks x 256 threads x MODMUL_CHAINS chains x
+// iters products of kind 0 (FP64, modulus q < 2^50), 1 (Shoup) or 2
+// (Montgomery); sink [blocks * 256].
+constexpr int MODMUL_CHAINS = 8;
+hipError_t launch_modmul_rate(int kind, int blocks, int iters, uint64_t q, uint64_t w, uint64_t ws, uint64_t ninv,
+                              uint64_t* sink, hipStream_t s);
 
 }  // namespace ks
