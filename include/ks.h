@@ -65,6 +65,7 @@ extern "C" {
 #define KS_ENOMEM -4  /* the library could not allocate its tables */
 #define KS_EUNSUP -5  /* the plan is not valid for these parameters */
 #define KS_EHIP -6    /* a HIP call failed; ks_last_hip_error() tells which */
+#define KS_ETOOBIG -7 /* ks_keyswitch_noalloc: the workspace exceeds KS_NOALLOC_SCRATCH_BYTES */
 
 #define KS_MAX_LIMBS 128 /* ell + k */
 #define KS_SET_P (-1)    /* ks_bconv source set: the P primes (target: Q) */
@@ -193,6 +194,22 @@ int ks_moddown(const ks_params* p, const uint64_t* acc, uint64_t* out, int batch
  * ks_workspace_bytes(p, batch, plan) bytes. d, evk and out must not overlap ws. */
 int ks_keyswitch(const ks_params* p, const uint64_t* d, const uint64_t* evk, uint64_t* out, int batch,
                  const ks_plan* plan, void* ws, void* stream);
+
+/* ks_keyswitch without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP-graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc). The workspace is a
+ * static device array of KS_NOALLOC_SCRATCH_BYTES inside the library, one per
+ * GPU, held from the first ks_params_create on that GPU until the process
+ * ends. The call takes the same arguments as ks_keyswitch minus ws and gives
+ * bit-identical output. KS_ETOOBIG (before anything is enqueued) when
+ * ks_workspace_bytes(p, batch, plan) exceeds the array: for instance up to
+ * 37 items of (2, 2^13, 6) and 5 of (2, 2^15, 10) fit under DPOB, and one of
+ * (4, 2^16, 32) under DSOB but not under DPOB. Every call on one GPU uses that GPU's one array: calls that overlap
+ * in time on one GPU (several streams, host threads or split plans of
+ * different calls) race and give wrong results; the caller orders them. */
+#define KS_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int ks_keyswitch_noalloc(const ks_params* p, const uint64_t* d, const uint64_t* evk, uint64_t* out, int batch,
+                         const ks_plan* plan, void* stream);
 
 /* HMUL (Background section: the product of two ciphertexts followed by
  * relinearisation): for a = (a0, a1) and b = (b0, b1), [batch][2][ell][N]

@@ -22,7 +22,8 @@ if not os.path.exists(LIB_PATH):
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-KS_OK, KS_EINVAL, KS_ENULL, KS_EALIGN, KS_ENOMEM, KS_EUNSUP, KS_EHIP = 0, -1, -2, -3, -4, -5, -6
+KS_OK, KS_EINVAL, KS_ENULL, KS_EALIGN, KS_ENOMEM, KS_EUNSUP, KS_EHIP, KS_ETOOBIG = 0, -1, -2, -3, -4, -5, -6, -7
+NOALLOC_SCRATCH_BYTES = 128 << 20  # KS_NOALLOC_SCRATCH_BYTES: the static workspace of keyswitch_noalloc
 KS_MAX_LIMBS = 128
 KS_SET_P = -1
 DSOB, DPOB, DSOC, DPOC, STAGED = 0, 1, 2, 3, 4
@@ -67,6 +68,7 @@ _lib.ks_modup.argtypes = [_vp, _vp, _vp, _i, _vp, _vp]
 _lib.ks_keymult.argtypes = [_vp, _vp, _vp, _vp, _i, _vp]
 _lib.ks_moddown.argtypes = [_vp, _vp, _vp, _i, _vp, _vp]
 _lib.ks_keyswitch.argtypes = [_vp, _vp, _vp, _vp, _i, ctypes.POINTER(Plan), _vp, _vp]
+_lib.ks_keyswitch_noalloc.argtypes = [_vp, _vp, _vp, _vp, _i, ctypes.POINTER(Plan), _vp]
 _lib.ks_hmul.argtypes = [_vp, _vp, _vp, _vp, _vp, _i, ctypes.POINTER(Plan), _vp, _vp]
 _lib.ks_hrot.argtypes = [_vp, _vp, _i, _vp, _vp, _i, ctypes.POINTER(Plan), _vp, _vp]
 _lib.ks_eval_workspace_bytes.argtypes = [_vp, _i, ctypes.POINTER(Plan), ctypes.POINTER(_sz)]
@@ -92,7 +94,8 @@ EXPORTED = ["ks_params_create", "ks_params_destroy", "ks_params_at_level", "ks_p
             "ks_default_plan", "ks_hmul", "ks_hrot", "ks_eval_workspace_bytes",
             "ks_ntt", "ks_intt", "ks_bconv", "ks_modup", "ks_keymult", "ks_moddown", "ks_keyswitch",
             "ks_launch_count", "ks_strerror", "ks_last_hip_error", "ks_trace_begin", "ks_trace_end",
-            "ks_graph_create", "ks_graph_launch", "ks_graph_destroy", "ks_modmul_rate", "ks_modmul_chains"]
+            "ks_graph_create", "ks_graph_launch", "ks_graph_destroy", "ks_modmul_rate", "ks_modmul_chains",
+            "ks_keyswitch_noalloc"]
 
 
 class KsError(RuntimeError):
@@ -279,6 +282,16 @@ class KsParams:
         self.check_keyswitch_args(d, evk, out, batch, ws, plan)
         _check(_lib.ks_keyswitch(self._h, _ptr(d), _ptr(evk), _ptr(out), batch,
                                  ctypes.byref(plan) if plan else None, _ptr(ws), _stream(stream)), "ks_keyswitch")
+
+    def keyswitch_noalloc(self, d, evk, out, batch, plan: Plan = None, stream=None):
+        """ks_keyswitch with the library's static scratch as workspace (no
+        allocation); calls that overlap on one GPU race."""
+        if batch > 0:
+            _need(d, batch * self.ell * self.n, "d")
+            _need(evk, self._key_words(), "evk")
+            _need(out, batch * 2 * self.ell * self.n, "out")
+        _check(_lib.ks_keyswitch_noalloc(self._h, _ptr(d), _ptr(evk), _ptr(out), batch,
+                                         ctypes.byref(plan) if plan else None, _stream(stream)), "ks_keyswitch_noalloc")
 
     def eval_workspace_bytes(self, batch: int, plan: Plan = None) -> int:
         b = _sz()

@@ -27,6 +27,14 @@ struct ks_params {
   std::mutex split;
 };
 
+// Scratch memory of ks_keyswitch_noalloc: a file-scope device array that
+// every GPU the library runs on holds until the process ends. In host code
+// `scratch` names a host-side stand-in, not device memory; the device address
+// of each GPU's copy is looked up once per device (hipGetSymbolAddress, with
+// that device current) when the first parameter handle is made there, and
+// only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[KS_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_hip_error = "none";
@@ -295,6 +303,29 @@ int run_fused(const ks_params* p, const ks_plan& plan, const uint64_t* d, const 
   return KS_OK;
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+// Device address of this device's scratch array; `device` must be current.
+hipError_t scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch[device] = static_cast<char*>(ptr);
+  return hipSuccess;
+}
+
+char* scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch[device];
+}
+
 }  // namespace
 
 extern "C" {
@@ -305,6 +336,7 @@ static int finish_params(ks_params* p, ks_params** out) {
   std::vector<uint64_t> blob;
   ks::build_tables(p->hp, blob, p->tb);
   hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) e = scratch_init(p->device);
   if (e == hipSuccess) e = hipMalloc(&p->blob, blob.size() * sizeof(uint64_t));
   if (e == hipSuccess) e = hipMemcpy(p->blob, blob.data(), blob.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
@@ -591,6 +623,23 @@ int ks_keyswitch(const ks_params* p, const uint64_t* d, const uint64_t* evk, uin
   return keyswitch_any(p, pl, d, evk, out, batch, reinterpret_cast<char*>(ws), (hipStream_t)stream);
 }
 
+int ks_keyswitch_noalloc(const ks_params* p, const uint64_t* d, const uint64_t* evk, uint64_t* out, int batch,
+                         const ks_plan* plan, void* stream) {
+  if (!p) return KS_ENULL;
+  if (!batch_fits(batch, std::max(2, p->hp.ndig)) || !coeffs_fit(p, batch, p->hp.nl)) return KS_EINVAL;
+  ks_plan pl;
+  int rc = resolve_plan(p, plan, pl);
+  if (rc != KS_OK) return rc;
+  if (batch == 0) return KS_OK;
+  if ((rc = check_ptr(d)) != KS_OK || (rc = check_ptr(evk)) != KS_OK || (rc = check_ptr(out)) != KS_OK) return rc;
+  if (workspace_total(p, batch, pl) > KS_NOALLOC_SCRATCH_BYTES) return KS_ETOOBIG;
+  char* ws = scratch_of(p->device);
+  if (!ws) return hip_fail(hipErrorInvalidSymbol);
+  // every workspace word the kernels read is written earlier in the same call,
+  // so the previous call's contents need no clearing
+  return keyswitch_any(p, pl, d, evk, out, batch, ws, (hipStream_t)stream);
+}
+
 // HMUL and HROT: element-wise pre-pass into the workspace, the KeySwitch of
 // one component straight into `out`, then the other part added to `out`
 // (under a fused plan the pre-pass and the add are folded into the
@@ -693,6 +742,7 @@ const char* ks_strerror(int code) {
     case KS_ENOMEM: return "out of memory";
     case KS_EUNSUP: return "plan not supported for these parameters";
     case KS_EHIP: return "HIP error";
+    case KS_ETOOBIG: return "workspace larger than the static scratch of ks_keyswitch_noalloc (KS_NOALLOC_SCRATCH_BYTES)";
     default: return "unknown error";
   }
 }

@@ -1,0 +1,87 @@
+"""ks_keyswitch_noalloc (the KeySwitch on the library's static scratch, no
+allocation) against ks_keyswitch, through the C ABI, bit for bit: two calls
+in a row on one GPU, the second with a smaller input, under several plans;
+oversized workspaces are refused before anything is enqueued."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import ciphertext_batch, uniform_key
+
+from gpu_util import dev, empty, first_mismatch, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ks():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2603_16692_amd as k
+    return k
+
+
+def _raw_noalloc(ks, G, d, evk, out, batch, plan):
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ks.raw_call("ks_keyswitch_noalloc", G._h, ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(evk.data_ptr()),
+                       ctypes.c_void_p(out.data_ptr()), batch, ctypes.byref(plan) if plan else None, stream)
+
+
+def _case(ks, dnum, log_n, ell, batch, seed):
+    G = ks.KsParams(dnum, log_n, ell)
+    d = dev(ciphertext_batch(G.moduli[:ell], G.n, batch, seed_base=seed))
+    evk = dev(uniform_key(G.moduli, G.n, G.ndig, seed=seed + 1))
+    return G, d, evk
+
+
+def test_noalloc_equals_keyswitch_on_two_calls(ks):
+    plans = [None, ks.make_plan(ks.DPOB, 1, 3, mfma=True), ks.make_plan(ks.STAGED),
+             ks.make_plan(ks.DSOC, 2, 2), ks.make_plan(ks.DPOB, 1, 3, split=True)]
+    # the larger call first, then a smaller one, which must not see the first call's scratch contents
+    big = _case(ks, 2, 15, 10, 4, 7100)
+    small = _case(ks, 2, 13, 6, 1, 7200)
+    for plan in plans:
+        for G, d, evk in (big, small):
+            batch = d.shape[0]
+            ref = empty((batch, 2, G.ell, G.n))
+            G.keyswitch(d, evk, ref, batch, G.workspace(batch, plan), plan)
+            torch.cuda.synchronize()
+            out = empty((batch, 2, G.ell, G.n))
+            out.fill_(-1)
+            before = torch.cuda.memory_allocated()
+            rc = _raw_noalloc(ks, G, d, evk, out, batch, plan)
+            assert rc == ks.KS_OK, (rc, plan)
+            assert torch.cuda.memory_allocated() == before
+            mm = first_mismatch(host(out), host(ref))
+            assert mm is None, f"{G} batch {batch} {plan}: {mm}"
+
+
+def test_noalloc_smaller_batch_of_the_same_set_and_oracle(ks):
+    G, d, evk = _case(ks, 3, 12, 7, 6, 7300)
+    P = oracle.Params(3, 12, 7)
+    for batch in (6, 2):
+        out = empty((batch, 2, G.ell, G.n))
+        dd = d[:batch].contiguous()
+        assert _raw_noalloc(ks, G, dd, evk, out, batch, None) == ks.KS_OK
+        ref = oracle.keyswitch(P, host(dd), host(evk).reshape(P.key_shape), batch)
+        assert first_mismatch(host(out), ref) is None, batch
+    # through the binding as well
+    out = empty((2, 2, G.ell, G.n))
+    G.keyswitch_noalloc(d[:2].contiguous(), evk, out, 2)
+    assert first_mismatch(host(out), oracle.keyswitch(P, host(d[:2].contiguous()), host(evk).reshape(P.key_shape),
+                                                      2)) is None
+
+
+def test_noalloc_refuses_workspaces_beyond_the_scratch(ks):
+    G, d, evk = _case(ks, 2, 15, 10, 1, 7400)
+    plan = ks.make_plan(ks.DPOB)
+    assert G.workspace_bytes(6, plan) > ks.NOALLOC_SCRATCH_BYTES >= G.workspace_bytes(5, plan)
+    big_d = empty((6, G.ell, G.n))
+    out = empty((6, 2, G.ell, G.n))
+    assert _raw_noalloc(ks, G, big_d, evk, out, 6, plan) == ks.KS_ETOOBIG
+    with pytest.raises(ks.KsError) as e:
+        G.keyswitch_noalloc(big_d, evk, out, 6, plan)
+    assert e.value.code == ks.KS_ETOOBIG
+    torch.cuda.synchronize()
