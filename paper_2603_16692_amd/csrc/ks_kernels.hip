@@ -1241,11 +1241,28 @@ hipError_t by_logr_mx(int log_r, A... a) {
 // the chip: -22% on (2, 2^13, 6) with one ciphertext).
 constexpr int loge_for(int logm) { return logm >= 12 ? 4 : (logm >= 6 ? 3 : (logm >= 4 ? 2 : 1)); }
 
+// Latency variant of a block pass: 4 elements per thread (8 at blocks of
+// 2^13), so that a block of 2^11 to 2^13 coefficients runs on 512 to 1024
+// threads. A launch whose default configuration would leave the chip short of
+// threads (a single small ciphertext) is bound by the serial chain of each
+// thread and by latencies that its few waves cannot hide; halving or
+// quartering the elements per thread shortens the chain and puts up to four
+// waves on every SIMD that runs a block.
+constexpr int loge_lat(int logm) { return logm >= 13 ? 3 : 2; }
+
+// Whether a launch of `wgs` workgroups of blocks of 2^logm with 2^loge
+// elements per thread has fewer than 2^18 threads (4 waves per SIMD over the
+// 1024 SIMDs): then its latency variant runs instead.
+inline bool use_lat(int logm, int loge, long wgs) {
+  return logm >= 8 && logm <= 13 && loge_lat(logm) < loge && wgs * (1L << (logm - loge)) < (1L << 18);
+}
+
 template <template <int, int> class F, typename... A>
-hipError_t by_logm(int log_m, A... a) {
+hipError_t by_logm(int log_m, long wgs, A... a) {
   switch (log_m) {
 #define KS_CASE(m) \
-  case m: return F<m, loge_for(m)>::run(a...);
+  case m:          \
+    return use_lat(m, loge_for(m), wgs) ? F<m, loge_lat(m)>::run(a...) : F<m, loge_for(m)>::run(a...);
     KS_CASE(3) KS_CASE(4) KS_CASE(5) KS_CASE(6) KS_CASE(7) KS_CASE(8) KS_CASE(9) KS_CASE(10) KS_CASE(11)
     KS_CASE(12) KS_CASE(13) KS_CASE(14)
 #undef KS_CASE
@@ -1262,10 +1279,12 @@ constexpr int loge_k3(int logm) { return logm >= 14 ? 4 : (logm >= 6 ? 3 : (logm
 constexpr int loge_k5(int logm) { return logm >= 13 ? 4 : loge_k3(logm); }
 
 template <template <int, int> class F, bool K5 = false, typename... A>
-hipError_t by_logm_k3(int log_m, A... a) {
+hipError_t by_logm_k3(int log_m, long wgs, A... a) {
   switch (log_m) {
-#define KS_CASE(m) \
-  case m: return F<m, K5 ? loge_k5(m) : loge_k3(m)>::run(a...);
+#define KS_CASE(m)                                                                   \
+  case m:                                                                            \
+    return use_lat(m, K5 ? loge_k5(m) : loge_k3(m), wgs) ? F<m, loge_lat(m)>::run(a...) \
+                                                         : F<m, K5 ? loge_k5(m) : loge_k3(m)>::run(a...);
     KS_CASE(3) KS_CASE(4) KS_CASE(5) KS_CASE(6) KS_CASE(7) KS_CASE(8) KS_CASE(9) KS_CASE(10) KS_CASE(11)
     KS_CASE(12) KS_CASE(13) KS_CASE(14)
 #undef KS_CASE
@@ -1496,24 +1515,26 @@ hipError_t launch_ntt(const DevTables& tb, int log_r, uint64_t* x, int first, in
   hipError_t e = hipSuccess;
   if (log_r > 0) e = by_logr<ColsFwd>(log_r, tb, x, first, nlimbs, items, log_m, s);
   if (e != hipSuccess) return e;
-  return by_logm<BlocksFwd>(log_m, tb, (const uint64_t*)x, x, first, nlimbs, items, 0, s);
+  return by_logm<BlocksFwd>(log_m, (long)(nlimbs << log_r) * items, tb, (const uint64_t*)x, x, first, nlimbs, items,
+                            0, s);
 }
 
 hipError_t launch_intt(const DevTables& tb, int log_r, uint64_t* x, int first, int nlimbs, int items, hipStream_t s) {
   const int log_m = tb.log_n - log_r;
-  hipError_t e = by_logm<BlocksInv>(log_m, tb, (const uint64_t*)x, x, first, nlimbs, items, log_r == 0 ? 1 : 0, s);
+  hipError_t e = by_logm<BlocksInv>(log_m, (long)(nlimbs << log_r) * items, tb, (const uint64_t*)x, x, first, nlimbs,
+                                    items, log_r == 0 ? 1 : 0, s);
   if (e != hipSuccess || log_r == 0) return e;
   return by_logr<ColsInv>(log_r, tb, x, first, nlimbs, items, log_m, s);
 }
 
 hipError_t launch_intt_blocks(const DevTables& tb, int log_r, const uint64_t* src, uint64_t* dst, int nlimbs,
                               int items, hipStream_t s) {
-  return by_logm<BlocksInv>(tb.log_n - log_r, tb, src, dst, 0, nlimbs, items, 0, s);
+  return by_logm<BlocksInv>(tb.log_n - log_r, (long)(nlimbs << log_r) * items, tb, src, dst, 0, nlimbs, items, 0, s);
 }
 
 hipError_t launch_eval_blocks(const DevTables& tb, int log_r, EvalIn ev, uint64_t* d2, uint64_t* t1, int items,
                               hipStream_t s) {
-  return by_logm<EvalBlocks>(tb.log_n - log_r, tb, ev, d2, t1, items, s);
+  return by_logm<EvalBlocks>(tb.log_n - log_r, (long)(tb.ell << log_r) * items, tb, ev, d2, t1, items, s);
 }
 
 hipError_t launch_modup_cols(const DevTables& tb, int log_r, const uint64_t* t1, uint64_t* ext1, int j0, int nj,
@@ -1528,16 +1549,16 @@ hipError_t launch_keymult_blocks(const DevTables& tb, int log_r, const uint64_t*
                                  const uint64_t* evk, uint64_t* acc, int j0, int j1, int nslots, int slot_stride,
                                  int tgt0, int tgt1, int items, int accumulate, int finalize, int q_part,
                                  hipStream_t s) {
-  return by_logm_k3<KeymultBlocks>(tb.log_n - log_r, tb, d, ext1, evk, acc, j0, j1, nslots, slot_stride, tgt0, tgt1,
-                                   items, accumulate, finalize, q_part, s);
+  return by_logm_k3<KeymultBlocks>(tb.log_n - log_r, (long)((tgt1 - tgt0) << log_r) * items, tb, d, ext1, evk, acc,
+                                   j0, j1, nslots, slot_stride, tgt0, tgt1, items, accumulate, finalize, q_part, s);
 }
 
 hipError_t launch_moddown_km_blocks(const DevTables& tb, int log_r, const uint64_t* d, const uint64_t* ext1,
                                     const uint64_t* evk, const uint64_t* t2, uint64_t* out, int j0, int j1,
                                     int nslots, int slot_stride, int tgt0, int tgt1, int items, EvalIn ev,
                                     hipStream_t s) {
-  return by_logm_k3<ModdownKmBlocks, true>(tb.log_n - log_r, tb, d, ext1, evk, t2, out, j0, j1, nslots, slot_stride, tgt0,
-                                     tgt1, items, ev, s);
+  return by_logm_k3<ModdownKmBlocks, true>(tb.log_n - log_r, (long)((tgt1 - tgt0) << log_r) * items, tb, d, ext1, evk,
+                                           t2, out, j0, j1, nslots, slot_stride, tgt0, tgt1, items, ev, s);
 }
 
 hipError_t launch_moddown_cols(const DevTables& tb, int log_r, const uint64_t* accp, uint64_t* t2, int tgt0,
@@ -1548,16 +1569,17 @@ hipError_t launch_moddown_cols(const DevTables& tb, int log_r, const uint64_t* a
 
 hipError_t launch_moddown_blocks(const DevTables& tb, int log_r, const uint64_t* t2, const uint64_t* acc,
                                  uint64_t* out, int tgt0, int tgt1, int items, EvalIn ev, hipStream_t s) {
-  return by_logm<ModdownBlocks>(tb.log_n - log_r, tb, t2, acc, out, tgt0, tgt1, items, ev, s);
+  return by_logm<ModdownBlocks>(tb.log_n - log_r, (long)((tgt1 - tgt0) << log_r) * items * 2, tb, t2, acc, out, tgt0,
+                                tgt1, items, ev, s);
 }
 
 hipError_t launch_ext_blocks(const DevTables& tb, int log_r, uint64_t* ext, int items, hipStream_t s) {
-  return by_logm<ExtBlocks>(tb.log_n - log_r, tb, ext, items, s);
+  return by_logm<ExtBlocks>(tb.log_n - log_r, (long)(tb.nl << log_r) * items * tb.ndig, tb, ext, items, s);
 }
 
 hipError_t launch_pblocks_inv(const DevTables& tb, int log_r, const uint64_t* acc, uint64_t* accp, int items,
                               hipStream_t s) {
-  return by_logm<PBlocksInv>(tb.log_n - log_r, tb, acc, accp, items, s);
+  return by_logm<PBlocksInv>(tb.log_n - log_r, (long)(tb.k << log_r) * items * 2, tb, acc, accp, items, s);
 }
 
 hipError_t launch_copy_digits(const DevTables& tb, const uint64_t* d, uint64_t* ext, int items, hipStream_t s) {
@@ -1652,6 +1674,47 @@ hipError_t launch_modmul_rate(int kind, int blocks, int iters, uint64_t q, uint6
     case 2: k_modmul_rate<2><<<dim3(blocks), dim3(256), 0, s>>>(iters, q, w, ws, ninv, qd, qinv, wd, sink); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// HBM copy probe: dst[i] = src[i] for `words` 64-bit words, each thread
+// moving 8 (kind 0) or 16 bytes (kind 1) per access with a grid-stride loop,
+// stores cached or non-temporal (nt). The practical streaming ceiling of the
+// access widths the kernels use.
+template <int WIDE, bool NT>
+__global__ __launch_bounds__(256) void k_copy_rate(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst,
+                                                   size_t words) {
+  const size_t stride = (size_t)gridDim.x * 256;
+  if (WIDE) {
+    const ulonglong2* s2 = reinterpret_cast<const ulonglong2*>(src);
+    ulonglong2* d2 = reinterpret_cast<ulonglong2*>(dst);
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < words / 2; i += stride) {
+      const ulonglong2 v = s2[i];
+      if (NT) {
+        __builtin_nontemporal_store(v.x, &d2[i].x);
+        __builtin_nontemporal_store(v.y, &d2[i].y);
+      } else {
+        d2[i] = v;
+      }
+    }
+  } else {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < words; i += stride) {
+      if (NT)
+        __builtin_nontemporal_store(src[i], dst + i);
+      else
+        dst[i] = src[i];
+    }
+  }
+}
+
+hipError_t launch_copy_rate(int kind, int nt, int blocks, const uint64_t* src, uint64_t* dst, size_t words,
+                            hipStream_t s) {
+  const dim3 g(blocks), t(256);
+  if (kind == 0 && !nt) k_copy_rate<0, false><<<g, t, 0, s>>>(src, dst, words);
+  else if (kind == 0) k_copy_rate<0, true><<<g, t, 0, s>>>(src, dst, words);
+  else if (kind == 1 && !nt) k_copy_rate<1, false><<<g, t, 0, s>>>(src, dst, words);
+  else if (kind == 1) k_copy_rate<1, true><<<g, t, 0, s>>>(src, dst, words);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
