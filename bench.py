@@ -39,8 +39,8 @@ OP_METRIC = {"keyswitch": "KeySwitch/s", "hmul": "HMUL/s", "hrot": "HROT/s"}
 # (sha256 below) and for the same workload and plan; otherwise "traffic" is null.
 # The rocprofv3 summaries it comes from are under profiles/.
 TRAFFIC = {"workload": "d4-n16-l32", "plan": "Plan(DPOB, chunks=1, log_r=4, mfma)", "kernel": "moddown_blocks",
-           "fetch_kib": 467280.6, "fetch_scale": 2.0, "write_kib": 262154.2, "write_scale": 1.0,
-           "sources_sha256": "dd078b0611658af0c463e3f65418ff57c13e1384102eaa681820ba8143068d74"}
+           "fetch_kib": 467276.3, "fetch_scale": 2.0, "write_kib": 262144.4, "write_scale": 1.0,
+           "sources_sha256": "fd9f553e5eb1e4f3d70372fdaaa5ac76563411d6ab39acc641d2da4de21565b9"}
 TRAFFIC_SOURCES = ["paper_2603_16692_amd/csrc/ks_kernels.hip", "paper_2603_16692_amd/csrc/ks_device.hpp"]
 
 
@@ -483,6 +483,14 @@ def main():
         roofline["measured_GBs"] = round(traffic / (dom_avg_ms / 1e3) / 1e9, 1)
         roofline["measured_frac"] = round(roofline["measured_GBs"] / HBM_PEAK_GBS, 4)
         roofline["wasted_traffic"] = round(traffic / alg_per_launch, 2)
+
+    # the practical streaming ceiling: the library's copy probe at the access
+    # widths the kernels use (8 and 16 bytes per lane), cached and
+    # non-temporal stores, over 1 GiB read + 1 GiB written
+    copy = {f"{8 * (k + 1)}B{'_nt' if nt else ''}": round(ks.copy_rate(k, nt) / 1e9, 1)
+            for k in (0, 1) for nt in (False, True)}
+    roofline["copy_ceiling_GBs"] = copy
+    roofline["frac_of_copy_ceiling"] = round(achieved / max(copy.values()), 4)
 
     roofline_alu = None
     nmm = kernel_modmuls(G, plan, batch, dominant) if args.op == "keyswitch" else None

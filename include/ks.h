@@ -297,6 +297,15 @@ int ks_trace_end(int* kinds, int capacity);
 int ks_modmul_rate(const ks_params* p, int kind, int blocks, int iters, uint64_t* sink, void* stream);
 int ks_modmul_chains(void);
 
+/* HBM copy probe (the practical streaming ceiling of the path): dst[i] =
+ * src[i] for `words` 64-bit words, device buffers owned by the caller that
+ * must not overlap, blocks x 256 threads in a grid-stride loop, each access
+ * 8 bytes (kind 0) or 16 bytes (kind 1, words even), stores non-temporal
+ * when nt != 0. Time it with events on `stream`; bytes moved = 16 * words.
+ * KS_EINVAL for another kind, an odd count with kind 1, or blocks outside
+ * [1, 2^20]. */
+int ks_copy_rate(int kind, int nt, int blocks, const uint64_t* src, uint64_t* dst, size_t words, void* stream);
+
 const char* ks_strerror(int code);
 /* Name of the HIP error behind the calling thread's last KS_EHIP. */
 const char* ks_last_hip_error(void);

@@ -75,6 +75,7 @@ _lib.ks_eval_workspace_bytes.argtypes = [_vp, _i, ctypes.POINTER(Plan), ctypes.P
 _lib.ks_launch_count.argtypes = [_vp, _i, ctypes.POINTER(Plan)]
 _lib.ks_modmul_rate.argtypes = [_vp, _i, _i, _i, _vp, _vp]
 _lib.ks_modmul_chains.restype = _i
+_lib.ks_copy_rate.argtypes = [_i, _i, _i, _vp, _vp, _sz, _vp]
 _lib.ks_strerror.argtypes = [_i]
 _lib.ks_strerror.restype = ctypes.c_char_p
 _lib.ks_last_hip_error.restype = ctypes.c_char_p
@@ -94,7 +95,7 @@ EXPORTED = ["ks_params_create", "ks_params_destroy", "ks_params_at_level", "ks_p
             "ks_default_plan", "ks_hmul", "ks_hrot", "ks_eval_workspace_bytes",
             "ks_ntt", "ks_intt", "ks_bconv", "ks_modup", "ks_keymult", "ks_moddown", "ks_keyswitch",
             "ks_launch_count", "ks_strerror", "ks_last_hip_error", "ks_trace_begin", "ks_trace_end",
-            "ks_graph_create", "ks_graph_launch", "ks_graph_destroy", "ks_modmul_rate", "ks_modmul_chains",
+            "ks_graph_create", "ks_graph_launch", "ks_graph_destroy", "ks_modmul_rate", "ks_modmul_chains", "ks_copy_rate",
             "ks_keyswitch_noalloc"]
 
 
@@ -343,6 +344,25 @@ class KsParams:
         key_nd = -(-self.key_ell // self.alpha)
         return {"d": (batch, ell, n), "ext": (batch, nd, nl, n), "evk": (key_nd, 2, self.key_ell + self.k, n),
                 "acc": (batch, 2, nl, n), "out": (batch, 2, ell, n)}
+
+
+def copy_rate(kind: int, nt: bool, words: int = 1 << 27, blocks: int = 4096, reps: int = 3) -> float:
+    """Measured HBM bytes per second (read + write) of the library's copy
+    probe over `words` words (ks_copy_rate), the best of `reps` launches."""
+    src = torch.ones(words, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    ev = HipEvents(2)
+    args = (kind, int(nt), blocks, _ptr(src), _ptr(dst), words, _stream(stream))
+    _check(_lib.ks_copy_rate(*args), "ks_copy_rate")
+    best = float("inf")
+    for _ in range(reps):
+        ev.record(0, stream)
+        _check(_lib.ks_copy_rate(*args), "ks_copy_rate")
+        ev.record(1, stream)
+        torch.cuda.synchronize()
+        best = min(best, ev.elapsed_ms(0, 1))
+    return 16 * words / (best / 1e3)
 
 
 class Graph:

@@ -733,6 +733,15 @@ int ks_modmul_rate(const ks_params* p, int kind, int blocks, int iters, uint64_t
 
 int ks_modmul_chains(void) { return ks::MODMUL_CHAINS; }
 
+int ks_copy_rate(int kind, int nt, int blocks, const uint64_t* src, uint64_t* dst, size_t words, void* stream) {
+  if (kind < 0 || kind > 1 || blocks < 1 || blocks > (1 << 20) || (kind == 1 && (words & 1))) return KS_EINVAL;
+  if (words == 0) return KS_OK;
+  int rc;
+  if ((rc = check_ptr(src)) != KS_OK || (rc = check_ptr(dst)) != KS_OK) return rc;
+  KS_TRY(ks::launch_copy_rate(kind, nt, blocks, src, dst, words, (hipStream_t)stream));
+  return KS_OK;
+}
+
 const char* ks_strerror(int code) {
   switch (code) {
     case KS_OK: return "ok";

@@ -64,6 +64,10 @@ hipError_t launch_keymult(const DevTables& tb, const uint64_t* ext, const uint64
 // iters products of kind 0 (FP64, modulus q < 2^50), 1 (Shoup) or 2
 // (Montgomery); sink [blocks * 256].
 constexpr int MODMUL_CHAINS = 8;
+// HBM copy probe: dst = src over `words` words (even for kind 1), 8 (kind 0)
+// or 16 (kind 1) bytes per access, non-temporal stores when nt != 0.
+hipError_t launch_copy_rate(int kind, int nt, int blocks, const uint64_t* src, uint64_t* dst, size_t words,
+                            hipStream_t s);
 hipError_t launch_modmul_rate(int kind, int blocks, int iters, uint64_t q, uint64_t w, uint64_t ws, uint64_t ninv,
                               uint64_t* sink, hipStream_t s);
 
