@@ -1,6 +1,8 @@
 """GPU tests of the runtime around the kernels: HIP-graph replay, the
 autotuner's plan choice, and the continuous-batching loop. Every result is
 compared bit for bit with an eager call, a batch-1 call, or the oracle."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -146,3 +148,38 @@ def test_serving_mix_of_the_four_benchmark_sets(ks):
                             ("d2-n13-l6", "d4-n16-l32"), plans)
     big = [r for r in done if r.set_name in ("d4-n16-l32", "d8-n17-l56")]
     assert big and any(r.batch_size > 1 for r in big), "no large-set request was batched"
+
+
+def test_probes_compute_what_they_time(ks):
+    # ks_modmul_rate (kind 0, FP64 products modulo the first Q prime): thread
+    # t's word is the sum over its chains c of (8t + c + 1) * w^iters mod q
+    G = ks.KsParams(2, 13, 6)
+    q = G.moduli[0]
+    w = q // 3 + 1
+    blocks, iters = 2, 7
+    sink = torch.zeros(blocks * 256, dtype=torch.int64, device="cuda")
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert ks.raw_call("ks_modmul_rate", G._h, 0, blocks, iters, ctypes.c_void_p(sink.data_ptr()), stream) == 0
+    chains = ks.raw_call("ks_modmul_chains")
+    got = host(sink)
+    wp = pow(w, iters, q)
+    for t in (0, 1, 255, 300, blocks * 256 - 1):
+        want = sum((chains * t + c + 1) * wp for c in range(chains)) % q
+        assert int(got[t]) == want, t
+    for kind in (1, 2):  # the integer products run and write every thread's word
+        sink.fill_(0)
+        assert ks.raw_call("ks_modmul_rate", G._h, kind, blocks, iters, ctypes.c_void_p(sink.data_ptr()), stream) == 0
+        assert int(torch.count_nonzero(sink)) == blocks * 256
+    assert ks.raw_call("ks_modmul_rate", G._h, 3, blocks, iters, ctypes.c_void_p(sink.data_ptr()), stream) == ks.KS_EINVAL
+    # ks_copy_rate copies every word, with 8- and 16-byte accesses, cached and non-temporal
+    src = torch.arange(1, 4097, dtype=torch.int64, device="cuda")
+    for kind in (0, 1):
+        for nt in (0, 1):
+            dst = torch.zeros_like(src)
+            rc = ks.raw_call("ks_copy_rate", kind, nt, 3, ctypes.c_void_p(src.data_ptr()),
+                             ctypes.c_void_p(dst.data_ptr()), ctypes.c_size_t(4096), stream)
+            assert rc == 0
+            assert torch.equal(dst, src), (kind, nt)
+    assert ks.raw_call("ks_copy_rate", 1, 0, 3, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                       ctypes.c_size_t(4095), stream) == ks.KS_EINVAL
+    torch.cuda.synchronize()
