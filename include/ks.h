@@ -31,7 +31,11 @@
  *     coefficient index fastest. Every data pointer is a device pointer owned
  *     by the caller and aligned to 256 bytes; the library never frees it.
  *     Inputs that are not canonical residues give unspecified (but in-bounds)
- *     results.
+ *     results in libks.so. The debug build libks_debug.so (same kernels and
+ *     symbols) first checks every input word a call reads against its
+ *     limb's prime and returns KS_EINVAL, with nothing else enqueued, if one
+ *     is not below it; that check waits for the device, so the debug build
+ *     synchronises on every call (a graph it captures skips the check).
  *   - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
  *     stream). Every call only enqueues work on it and returns without
  *     synchronising; enqueued work may be captured into a HIP graph.

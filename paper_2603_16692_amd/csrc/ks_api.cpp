@@ -25,6 +25,10 @@ struct ks_params {
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
   std::mutex split;
+  // Debug build only: device flag word followed by the row table of the input
+  // check (see dbg_check), serialised by dbg_mu.
+  int* dbg = nullptr;
+  std::mutex dbg_mu;
 };
 
 // Scratch memory of ks_keyswitch_noalloc: a file-scope device array that
@@ -191,6 +195,67 @@ void chunk_range(int n, int c, int i, int& a, int& b) {
     if (e_ != hipSuccess) return hip_fail(e_); \
   } while (0)
 
+// Rows of the input check: one limb index per row of an input (negative: a
+// row the call does not read), for the debug build's canonical-input test.
+size_t dbg_rows_max(const ks::HostParams& hp, const ks::DevTables& tb) {
+  return std::max({(size_t)hp.ndig * 2 * tb.evk_nl, (size_t)hp.ndig * hp.nl, (size_t)2 * hp.nl});
+}
+
+#ifdef KS_DEBUG_CHECKS
+thread_local bool g_capturing = false;
+
+// The Q limbs of a polynomial, `copies` times ([copies][ell] rows).
+std::vector<int> rows_q(const ks_params* p, int copies) {
+  std::vector<int> r;
+  for (int c = 0; c < copies; ++c)
+    for (int i = 0; i < p->hp.ell; ++i) r.push_back(i);
+  return r;
+}
+// Limbs first .. first + n - 1 of the extended basis, `copies` times.
+std::vector<int> rows_range(int first, int n, int copies) {
+  std::vector<int> r;
+  for (int c = 0; c < copies; ++c)
+    for (int i = 0; i < n; ++i) r.push_back(first + i);
+  return r;
+}
+// The key rows a call reads: digits 0 .. ndig-1 of [ndig_top][2][evk_nl][N];
+// row t < ell is limb t, row evk_p0 + m is P limb m, other rows are unread.
+std::vector<int> rows_key(const ks_params* p) {
+  const ks::DevTables& tb = p->tb;
+  std::vector<int> r;
+  for (int j = 0; j < p->hp.ndig; ++j)
+    for (int c = 0; c < 2; ++c)
+      for (int row = 0; row < tb.evk_nl; ++row)
+        r.push_back(row < tb.ell ? row : (row >= tb.evk_p0 ? tb.ell + (row - tb.evk_p0) : -1));
+  return r;
+}
+
+// Debug build: KS_EINVAL unless every word x reads is a canonical residue of
+// its row's prime. Enqueues a read-only check on s and waits for it (so a
+// debug build synchronises on every call); skipped while a graph is captured.
+int dbg_check(const ks_params* p, const uint64_t* x, const std::vector<int>& rows, int items, hipStream_t s) {
+  if (g_capturing || items <= 0 || rows.empty()) return KS_OK;
+  std::lock_guard<std::mutex> lock(const_cast<ks_params*>(p)->dbg_mu);
+  const int zero = 0;
+  int flag = 0;
+  KS_TRY(hipMemcpyAsync(p->dbg + 1, rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  KS_TRY(hipMemcpyAsync(p->dbg, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+  KS_TRY(ks::launch_check_rows(p->tb, x, p->dbg + 1, (int)rows.size(), items, rows.size() * p->hp.n, p->dbg, s));
+  KS_TRY(hipMemcpyAsync(&flag, p->dbg, sizeof(int), hipMemcpyDeviceToHost, s));
+  KS_TRY(hipStreamSynchronize(s));
+  return flag ? KS_EINVAL : KS_OK;
+}
+#define KS_DEBUG_CHECK(expr)              \
+  do {                                    \
+    const int rc_ = (expr);               \
+    if (rc_ != KS_OK) return rc_;         \
+  } while (0)
+#else
+#define KS_DEBUG_CHECK(expr) \
+  do {                       \
+  } while (0)
+#endif
+
 int run_modup(const ks_params* p, const ks_plan& plan, const uint64_t* d, uint64_t* ext, int batch, uint64_t* t1,
               hipStream_t s) {
   const ks::DevTables& tb = p->tb;
@@ -338,9 +403,13 @@ static int finish_params(ks_params* p, ks_params** out) {
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess) e = scratch_init(p->device);
   if (e == hipSuccess) e = hipMalloc(&p->blob, blob.size() * sizeof(uint64_t));
+#ifdef KS_DEBUG_CHECKS
+  if (e == hipSuccess) e = hipMalloc(&p->dbg, sizeof(int) * (1 + dbg_rows_max(p->hp, p->tb)));
+#endif
   if (e == hipSuccess) e = hipMemcpy(p->blob, blob.data(), blob.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     if (p->blob) (void)hipFree(p->blob);
+    if (p->dbg) (void)hipFree(p->dbg);
     delete p;
     return e == hipErrorOutOfMemory ? KS_ENOMEM : hip_fail(e);
   }
@@ -411,6 +480,7 @@ void ks_params_destroy(ks_params* p) {
   if (p->fork) (void)hipEventDestroy(p->fork);
   if (p->join) (void)hipEventDestroy(p->join);
   if (p->blob) (void)hipFree(p->blob);
+  if (p->dbg) (void)hipFree(p->dbg);
   delete p;
 }
 
@@ -491,6 +561,7 @@ int ks_ntt(const ks_params* p, uint64_t* x, int basis_first, int n_limbs, int ba
   if (rc != KS_OK) return rc;
   if (n_limbs == 0 || batch == 0) return KS_OK;
   if ((rc = check_ptr(x)) != KS_OK) return rc;
+  KS_DEBUG_CHECK(dbg_check(p, x, rows_range(basis_first, n_limbs, 1), batch, (hipStream_t)stream));
   KS_TRY(traced(KS_K_NTT, (hipStream_t)stream, [&] { return ks::launch_ntt(p->tb, default_log_r(p->hp.log_n), x, basis_first, n_limbs, batch, (hipStream_t)stream); }));
   return KS_OK;
 }
@@ -501,6 +572,7 @@ int ks_intt(const ks_params* p, uint64_t* x, int basis_first, int n_limbs, int b
   if (rc != KS_OK) return rc;
   if (n_limbs == 0 || batch == 0) return KS_OK;
   if ((rc = check_ptr(x)) != KS_OK) return rc;
+  KS_DEBUG_CHECK(dbg_check(p, x, rows_range(basis_first, n_limbs, 1), batch, (hipStream_t)stream));
   KS_TRY(traced(KS_K_NTT, (hipStream_t)stream, [&] { return ks::launch_intt(p->tb, default_log_r(p->hp.log_n), x, basis_first, n_limbs, batch, (hipStream_t)stream); }));
   return KS_OK;
 }
@@ -512,6 +584,13 @@ int ks_bconv(const ks_params* p, const uint64_t* src, int src_set, uint64_t* dst
   if (batch == 0) return KS_OK;
   int rc;
   if ((rc = check_ptr(src)) != KS_OK || (rc = check_ptr(dst)) != KS_OK) return rc;
+#ifdef KS_DEBUG_CHECKS
+  {
+    const int lo = src_set == KS_SET_P ? p->hp.ell : src_set * p->hp.alpha;
+    const int ns = src_set == KS_SET_P ? p->hp.k : std::min(lo + p->hp.alpha, p->hp.ell) - lo;
+    KS_DEBUG_CHECK(dbg_check(p, src, rows_range(lo, ns, 1), batch, (hipStream_t)stream));
+  }
+#endif
   KS_TRY(traced(KS_K_BCONV, (hipStream_t)stream, [&] { return ks::launch_bconv(p->tb, src, src_set, dst, batch, (hipStream_t)stream); }));
   return KS_OK;
 }
@@ -522,6 +601,7 @@ int ks_modup(const ks_params* p, const uint64_t* d, uint64_t* ext, int batch, vo
   if (batch == 0) return KS_OK;
   int rc;
   if ((rc = check_ptr(d)) != KS_OK || (rc = check_ptr(ext)) != KS_OK || (rc = check_ptr(ws)) != KS_OK) return rc;
+  KS_DEBUG_CHECK(dbg_check(p, d, rows_q(p, 1), batch, (hipStream_t)stream));
   ks_plan pl;
   const ks_plan staged{KS_STAGED, 1, -1, 0, 0};
   if ((rc = resolve_plan(p, &staged, pl)) != KS_OK) return rc;
@@ -535,6 +615,8 @@ int ks_keymult(const ks_params* p, const uint64_t* ext, const uint64_t* evk, uin
   if (batch == 0) return KS_OK;
   int rc;
   if ((rc = check_ptr(ext)) != KS_OK || (rc = check_ptr(evk)) != KS_OK || (rc = check_ptr(acc)) != KS_OK) return rc;
+  KS_DEBUG_CHECK(dbg_check(p, ext, rows_range(0, p->hp.nl, p->hp.ndig), batch, (hipStream_t)stream));
+  KS_DEBUG_CHECK(dbg_check(p, evk, rows_key(p), 1, (hipStream_t)stream));
   KS_TRY(traced(KS_K_KEYMULT, (hipStream_t)stream, [&] { return ks::launch_keymult(p->tb, ext, evk, acc, batch, (hipStream_t)stream); }));
   return KS_OK;
 }
@@ -545,6 +627,7 @@ int ks_moddown(const ks_params* p, const uint64_t* acc, uint64_t* out, int batch
   if (batch == 0) return KS_OK;
   int rc;
   if ((rc = check_ptr(acc)) != KS_OK || (rc = check_ptr(out)) != KS_OK || (rc = check_ptr(ws)) != KS_OK) return rc;
+  KS_DEBUG_CHECK(dbg_check(p, acc, rows_range(0, p->hp.nl, 2), batch, (hipStream_t)stream));
   ks_plan pl;
   const ks_plan staged{KS_STAGED, 1, -1, 0, 0};
   if ((rc = resolve_plan(p, &staged, pl)) != KS_OK) return rc;
@@ -620,6 +703,8 @@ int ks_keyswitch(const ks_params* p, const uint64_t* d, const uint64_t* evk, uin
   if ((rc = check_ptr(d)) != KS_OK || (rc = check_ptr(evk)) != KS_OK || (rc = check_ptr(out)) != KS_OK ||
       (rc = check_ptr(ws)) != KS_OK)
     return rc;
+  KS_DEBUG_CHECK(dbg_check(p, d, rows_q(p, 1), batch, (hipStream_t)stream));
+  KS_DEBUG_CHECK(dbg_check(p, evk, rows_key(p), 1, (hipStream_t)stream));
   return keyswitch_any(p, pl, d, evk, out, batch, reinterpret_cast<char*>(ws), (hipStream_t)stream);
 }
 
@@ -633,6 +718,8 @@ int ks_keyswitch_noalloc(const ks_params* p, const uint64_t* d, const uint64_t* 
   if (batch == 0) return KS_OK;
   if ((rc = check_ptr(d)) != KS_OK || (rc = check_ptr(evk)) != KS_OK || (rc = check_ptr(out)) != KS_OK) return rc;
   if (workspace_total(p, batch, pl) > KS_NOALLOC_SCRATCH_BYTES) return KS_ETOOBIG;
+  KS_DEBUG_CHECK(dbg_check(p, d, rows_q(p, 1), batch, (hipStream_t)stream));
+  KS_DEBUG_CHECK(dbg_check(p, evk, rows_key(p), 1, (hipStream_t)stream));
   char* ws = scratch_of(p->device);
   if (!ws) return hip_fail(hipErrorInvalidSymbol);
   // every workspace word the kernels read is written earlier in the same call,
@@ -676,6 +763,9 @@ int ks_hmul(const ks_params* p, const uint64_t* a, const uint64_t* b, const uint
   if (rc != KS_OK) return rc;
   if (batch == 0) return KS_OK;
   if ((rc = eval_check(p, a, b, evk, out, ws)) != KS_OK) return rc;
+  KS_DEBUG_CHECK(dbg_check(p, a, rows_q(p, 2), batch, (hipStream_t)stream));
+  KS_DEBUG_CHECK(dbg_check(p, b, rows_q(p, 2), batch, (hipStream_t)stream));
+  KS_DEBUG_CHECK(dbg_check(p, evk, rows_key(p), 1, (hipStream_t)stream));
   hipStream_t s = (hipStream_t)stream;
   const size_t LN = (size_t)p->hp.ell * p->hp.n;
   uint64_t* t01 = reinterpret_cast<uint64_t*>(ws);
@@ -699,6 +789,8 @@ int ks_hrot(const ks_params* p, const uint64_t* ct, int galois, const uint64_t* 
   if (rc != KS_OK) return rc;
   if (batch == 0) return KS_OK;
   if ((rc = eval_check(p, ct, nullptr, evk, out, ws)) != KS_OK) return rc;
+  KS_DEBUG_CHECK(dbg_check(p, ct, rows_q(p, 2), batch, (hipStream_t)stream));
+  KS_DEBUG_CHECK(dbg_check(p, evk, rows_key(p), 1, (hipStream_t)stream));
   hipStream_t s = (hipStream_t)stream;
   const size_t LN = (size_t)p->hp.ell * p->hp.n;
   uint64_t* t01 = reinterpret_cast<uint64_t*>(ws);  // sigma(c0) in component 0
@@ -779,7 +871,13 @@ int ks_graph_create(const ks_params* p, const uint64_t* d, const uint64_t* evk, 
   g_trace = Trace{};
   hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
+#ifdef KS_DEBUG_CHECKS
+    g_capturing = true;  // the eager call above checked the inputs; a capture cannot wait on the device
+#endif
     rc = ks_keyswitch(p, d, evk, out, batch, plan, ws, stream);
+#ifdef KS_DEBUG_CHECKS
+    g_capturing = false;
+#endif
     hipGraph_t captured = nullptr;
     const hipError_t e2 = hipStreamEndCapture(s, &captured);
     g->graph = captured;

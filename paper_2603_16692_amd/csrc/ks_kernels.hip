@@ -1677,6 +1677,27 @@ hipError_t launch_modmul_rate(int kind, int blocks, int iters, uint64_t q, uint6
   return hipGetLastError();
 }
 
+// Input check of the debug build: flag[0] = 1 if some word of x is not a
+// canonical residue of its row's prime. x holds `items` blocks of item_words
+// words; row r of an item (N words at offset r * N) belongs to limb
+// row_limb[r] of the extended basis (negative: a row the call does not read).
+// Grid: (ceil(N / 256), rows, items).
+__global__ __launch_bounds__(256) void k_check_rows(DevTables tb, const uint64_t* x, const int* row_limb,
+                                                    size_t item_words, int* flag) {
+  const size_t N = (size_t)1 << tb.log_n;
+  const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const int limb = row_limb[blockIdx.y];
+  if (c >= N || limb < 0) return;
+  if (x[(size_t)blockIdx.z * item_words + (size_t)blockIdx.y * N + c] >= tb.limb[limb].q) *flag = 1;
+}
+
+hipError_t launch_check_rows(const DevTables& tb, const uint64_t* x, const int* row_limb, int rows, int items,
+                             size_t item_words, int* flag, hipStream_t s) {
+  const unsigned n = 1u << tb.log_n;
+  k_check_rows<<<dim3((n + 255) / 256, rows, items), dim3(256), 0, s>>>(tb, x, row_limb, item_words, flag);
+  return hipGetLastError();
+}
+
 // HBM copy probe: dst[i] = src[i] for `words` 64-bit words, each thread
 // moving 8 (kind 0) or 16 bytes (kind 1) per access with a grid-stride loop,
 // stores cached or non-temporal (nt). The practical streaming ceiling of the

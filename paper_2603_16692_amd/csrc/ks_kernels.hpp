@@ -64,6 +64,10 @@ hipError_t launch_keymult(const DevTables& tb, const uint64_t* ext, const uint64
 // iters products of kind 0 (FP64, modulus q < 2^50), 1 (Shoup) or 2
 // (Montgomery); sink [blocks * 256].
 constexpr int MODMUL_CHAINS = 8;
+// Debug-build input check: *flag = 1 if a word of x [items][rows][N] (item
+// stride item_words) is not below the prime of its row (row_limb[r] < 0: skip).
+hipError_t launch_check_rows(const DevTables& tb, const uint64_t* x, const int* row_limb, int rows, int items,
+                             size_t item_words, int* flag, hipStream_t s);
 // HBM copy probe: dst = src over `words` words (even for kind 1), 8 (kind 0)
 // or 16 (kind 1) bytes per access, non-temporal stores when nt != 0.
 hipError_t launch_copy_rate(int kind, int nt, int blocks, const uint64_t* src, uint64_t* dst, size_t words,

@@ -21,9 +21,11 @@ def test_header_declares_the_path():
 
 
 def test_library_exports_every_declared_symbol():
-    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2603_16692_amd", "libks.so"))
-    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
-    assert not missing, missing
+    # the release library and its debug twin (canonical-input checks)
+    for name in ("libks.so", "libks_debug.so"):
+        lib = ctypes.CDLL(os.path.join(ROOT, "paper_2603_16692_amd", name))
+        missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+        assert not missing, (name, missing)
 
 
 def test_binding_loads_and_lists_exports():
