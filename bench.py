@@ -228,7 +228,7 @@ def main():
     ap.add_argument("--level", type=int, default=0,
                     help="KeySwitch at this many Q limbs with the top-level key (default: the top level)")
     ap.add_argument("--plan", default="",
-                    help="dataflow[,chunks[,log_r[,options]]], options mfma, split and tile=<items per pass> "
+                    help="dataflow[,chunks[,log_r[,options]]], options mfma, split, hoist and tile=<items per pass> "
                          "joined by '+', e.g. DPOB or DSOC,2,3 or DPOB,1,4,mfma+split or DPOB,1,3,mfma+tile=8")
     ap.add_argument("--h2d", action="store_true",
                     help="with --op hmul: also time HMUL with its inputs copied from pinned host memory (overlapped)")
@@ -295,7 +295,7 @@ def main():
         log_r = int(parts[2]) if len(parts) > 2 else -1
         opts = parts[3].split("+") if len(parts) > 3 else []
         tile = next((int(o[5:]) for o in opts if o.startswith("tile=")), 0)
-        plan = ks.make_plan(df, chunks, log_r, "mfma" in opts, "split" in opts, tile)
+        plan = ks.make_plan(df, chunks, log_r, "mfma" in opts, "split" in opts, tile, "hoist" in opts)
 
     to_dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda")
     lv = G.ell

@@ -88,7 +88,7 @@ typedef struct {
   int chunks;   /* output partitions for KS_DSOC / KS_DPOC (1..64), else ignored */
   int log_r;    /* NTT split N = 2^log_r * M: 2^log_r rows per column, blocks of M
                    coefficients (0 = one block pass, up to 5); negative = default */
-  int flags;    /* KS_PLAN_MFMA_BCONV | KS_PLAN_SPLIT_STREAMS; other bits are rejected (KS_EUNSUP) */
+  int flags;    /* KS_PLAN_MFMA_BCONV | KS_PLAN_SPLIT_STREAMS | KS_PLAN_HOIST_FWD; other bits are rejected (KS_EUNSUP) */
   int batch_tile; /* items per pass: 0 = the whole batch in one pass; else the batch runs in
                      consecutive passes of at most batch_tile items in stream order, each reusing
                      a workspace (and cache footprint) sized for one pass; negative = KS_EUNSUP */
@@ -116,6 +116,16 @@ typedef struct {
    with one handle from several host threads are serialised around this
    fork and join. */
 #define KS_PLAN_SPLIT_STREAMS 2
+
+/* Plan flag, with KS_DPOB only (KS_EUNSUP otherwise): run the forward block
+   pass of the raised digits as a launch of its own (in place in the
+   workspace), then the KeyMult of the P limbs with their inverse block pass,
+   and ModDown's last pass with the Q-limb KeyMult, each with one output
+   component per workgroup: 6 launches instead of 5, twice the workgroups per
+   KeyMult launch and at most one transform per workgroup, for the short
+   critical path a single small ciphertext needs (the raised digits make one
+   more round trip through memory). The output is identical. */
+#define KS_PLAN_HOIST_FWD 4
 
 typedef struct {
   int n, log_n, ell, k, alpha, dnum, ndig;

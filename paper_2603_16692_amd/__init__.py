@@ -30,6 +30,7 @@ DSOB, DPOB, DSOC, DPOC, STAGED = 0, 1, 2, 3, 4
 DATAFLOW_NAMES = {DSOB: "DSOB", DPOB: "DPOB", DSOC: "DSOC", DPOC: "DPOC", STAGED: "STAGED"}
 PLAN_MFMA_BCONV = 1  # ks_plan.flags: BConv as an exact int8 product on the matrix cores
 PLAN_SPLIT_STREAMS = 2  # ks_plan.flags: the two halves of a batch on two streams
+PLAN_HOIST_FWD = 4  # ks_plan.flags (DPOB): the raised digits' forward block pass as a launch of its own
 
 
 class Plan(ctypes.Structure):
@@ -39,6 +40,7 @@ class Plan(ctypes.Structure):
     def __repr__(self):
         mx = ", mfma" if self.flags & PLAN_MFMA_BCONV else ""
         sp = ", split" if self.flags & PLAN_SPLIT_STREAMS else ""
+        sp += ", hoist" if self.flags & PLAN_HOIST_FWD else ""
         tl = f", tile={self.batch_tile}" if self.batch_tile else ""
         return (f"Plan({DATAFLOW_NAMES.get(self.dataflow, self.dataflow)}, chunks={self.chunks}, "
                 f"log_r={self.log_r}{mx}{sp}{tl})")
@@ -146,11 +148,13 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def make_plan(dataflow=DPOB, chunks=1, log_r=-1, mfma=False, split=False, tile=0):
+def make_plan(dataflow=DPOB, chunks=1, log_r=-1, mfma=False, split=False, tile=0, hoist=False):
     """A plan; log_r < 0 selects the library's default NTT split; mfma selects
     the int8 matrix-core BConv; split runs the two halves of a batch on two
-    streams; tile > 0 runs the batch in passes of at most `tile` items."""
-    return Plan(dataflow, chunks, log_r, (PLAN_MFMA_BCONV if mfma else 0) | (PLAN_SPLIT_STREAMS if split else 0), tile)
+    streams; tile > 0 runs the batch in passes of at most `tile` items; hoist
+    (DPOB only) runs the raised digits' forward block pass as its own launch."""
+    flags = (PLAN_MFMA_BCONV if mfma else 0) | (PLAN_SPLIT_STREAMS if split else 0) | (PLAN_HOIST_FWD if hoist else 0)
+    return Plan(dataflow, chunks, log_r, flags, tile)
 
 
 class KsParams:

@@ -22,8 +22,8 @@ import statistics
 
 import torch
 
-from . import (DPOB, DPOC, DSOB, DSOC, STAGED, DATAFLOW_NAMES, PLAN_MFMA_BCONV, PLAN_SPLIT_STREAMS, HipEvents,
-               KsError, make_plan)
+from . import (DPOB, DPOC, DSOB, DSOC, STAGED, DATAFLOW_NAMES, HipEvents,
+               KsError, Plan, make_plan)
 
 WORD = 8
 MALL_BYTES = 256 << 20
@@ -62,6 +62,8 @@ def candidate_plans(params, batch: int, chunk_range=CHUNK_RANGE, mfma=(False, Tr
                     continue
                 for df in (DSOB, DPOB, STAGED):
                     plans.append(make_plan(df, 1, log_r, mx, sp))
+                    if df == DPOB:  # the forward pass of the raised digits as a launch of its own
+                        plans.append(make_plan(df, 1, log_r, mx, sp, hoist=True))
                     if df != DSOB and not sp:
                         plans += [make_plan(df, 1, log_r, mx, sp, t) for t in tiles]
                 for df in (DSOC, DPOC):
@@ -198,7 +200,7 @@ def cached_plan(params, batch: int, cache: dict):
     df, chunks, log_r = e["plan"][:3]
     flags = e["plan"][3] if len(e["plan"]) > 3 else 0
     tile = e["plan"][4] if len(e["plan"]) > 4 else 0
-    p = make_plan(df, chunks, log_r, bool(flags & PLAN_MFMA_BCONV), bool(flags & PLAN_SPLIT_STREAMS), tile)
+    p = Plan(df, chunks, log_r, flags, tile)
     try:
         params.workspace_bytes(batch, p)
     except KsError:

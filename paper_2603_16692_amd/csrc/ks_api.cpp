@@ -100,7 +100,8 @@ int resolve_plan(const ks_params* p, const ks_plan* in, ks_plan& out) {
   } else {
     out = ks_plan{KS_DPOB, 1, -1, 0, 0};
   }
-  if (out.flags & ~(KS_PLAN_MFMA_BCONV | KS_PLAN_SPLIT_STREAMS)) return KS_EUNSUP;
+  if (out.flags & ~(KS_PLAN_MFMA_BCONV | KS_PLAN_SPLIT_STREAMS | KS_PLAN_HOIST_FWD)) return KS_EUNSUP;
+  if ((out.flags & KS_PLAN_HOIST_FWD) && out.dataflow != KS_DPOB) return KS_EUNSUP;
   if (out.batch_tile < 0) return KS_EUNSUP;
   if (out.dataflow < KS_DSOB || out.dataflow > KS_STAGED) return KS_EUNSUP;
   if (out.log_r < 0) {
@@ -315,6 +316,27 @@ int run_fused(const ks_params* p, const ks_plan& plan, const uint64_t* d, const 
   else if (run)
     KS_TRY(traced(KS_K_INTT_D, s, [&] { return ks::launch_intt_blocks(tb, plan.log_r, d, t1, tb.ell, batch, s); }));
   ++count;
+  if (plan.flags & KS_PLAN_HOIST_FWD) {
+    // DPOB with the raised digits' forward block pass in a launch of its own,
+    // then KeyMult and ModDown's tail one component per workgroup
+    if (run) {
+      KS_TRY(traced(KS_K_MODUP_COLS, s, [&] {
+        return ks::launch_modup_cols(tb, plan.log_r, t1, ext1, 0, tb.ndig, L.nslots, 1, 0, tb.nl, batch, mx, s);
+      }));
+      KS_TRY(traced(KS_K_EXT_BLOCKS, s, [&] { return ks::launch_ext_blocks(tb, plan.log_r, ext1, batch, s); }));
+      KS_TRY(traced(KS_K_KEYMULT_BLOCKS, s, [&] {
+        return ks::launch_keymult_pre(tb, plan.log_r, ext1, evk, acc, batch, s);
+      }));
+      KS_TRY(traced(KS_K_MODDOWN_COLS, s, [&] {
+        return ks::launch_moddown_cols(tb, plan.log_r, acc, t2, 0, tb.ell, batch, mx, s);
+      }));
+      KS_TRY(traced(KS_K_MODDOWN_BLOCKS, s, [&] {
+        return ks::launch_moddown_pre(tb, plan.log_r, d, ext1, evk, t2, out, batch, ev, s);
+      }));
+    }
+    if (launches) *launches = count + 5;
+    return KS_OK;
+  }
   for (int ci = 0; ci < c; ++ci) {
     int a, b;
     chunk_range(tb.nl, c, ci, a, b);

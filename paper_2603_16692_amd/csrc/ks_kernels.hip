@@ -1036,6 +1036,124 @@ __global__ __launch_bounds__((1 << (LOGM - LOGE)), (LOGE == 3 && LOGM >= 12) ? 4
     finish(std::integral_constant<int, 2>{});
 }
 
+// --------------------------------- hoisted forward passes (KS_PLAN_HOIST_FWD)
+
+// The digit-parallel KeyMult and ModDown tail when the raised digits are
+// already forward-transformed (k_ext_blocks ran on ext1 in place, canonical
+// residues in natural order): every workgroup then handles one component of
+// one (limb, block, item) and runs at most one transform, so a launch has
+// twice the workgroups of K3 / K5 and a quarter to a third of their serial
+// chain, which is what a single small ciphertext needs.
+
+// P limbs: acc_c[t] = sum_j ext1[j][t] * evk[j][c][t] (Montgomery products,
+// running sums in [0, 2q)), then the inverse block pass; stored like K3's
+// finalize (accp in [0, 2q), first-round layout). Tile (P limb, block),
+// item (item, component).
+template <int LOGM, int LOGE>
+__global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_keymult_pre(DevTables tb, const uint64_t* ext1,
+                                                                      const uint64_t* evk, uint64_t* acc, int items2) {
+  using B = BlockNtt<LOGM, LOGE>;
+  extern __shared__ uint64_t lds[];
+  const size_t N = (size_t)1 << tb.log_n;
+  const int R = (int)(N >> LOGM);
+  const Tile tl = xcd_tile(R * tb.k, items2);
+  if (!tl.valid) return;
+  const int tid = threadIdx.x, b = tl.tile % R;
+  const int t = tb.ell + tl.tile / R;
+  const int item = tl.item >> 1, c = tl.item & 1;
+  const LimbC L = tb.limb[t];
+  const int nl = tb.nl;
+  const size_t boff = (size_t)b * B::M;
+  uint64_t s[B::E];
+#pragma unroll
+  for (int i = 0; i < B::E; ++i) s[i] = 0;
+  for (int j = 0; j < tb.ndig; ++j) {
+    const uint64_t* src = ext1 + (((size_t)item * tb.ndig + j) * nl + t) * N + boff;
+    const uint64_t* key = evk + key_row(tb, j, c, t) * N + boff;
+#pragma unroll
+    for (int i = 0; i < B::E; ++i) {
+      const int x = B::cl_pos(tid, i);
+      s[i] += mont_mul(src[x], key[x], L.q, L.mont_ninv);
+      s[i] = s[i] >= L.two_q ? s[i] - L.two_q : s[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < B::E; ++i) s[i] = reduce2(mont_mul(s[i], L.r2, L.q, L.mont_ninv), L.q);
+  inv_opaque<B>(ari(tb, L, t, true), s, lds, tid, (uint32_t)R + b);
+  uint64_t* a = acc + (((size_t)item * 2 + c) * nl + t) * N + boff;
+#pragma unroll
+  for (int i = 0; i < B::E; ++i) a[B::fr_pos(tid, i)] = s[i];
+}
+
+// Q limbs: out_c[i] = (sum_j ext_j[i] * evk[j][c][i] - NTT(t2_c)[i]) * P^-1
+// with ext_j = d for the digit that owns limb i (d, or a1 b1 / sigma(c1) for
+// HMUL / HROT, natural order) and the pre-transformed ext1 slot otherwise;
+// HMUL / HROT add their other terms of component c. Tile (Q limb, block),
+// item (item, component).
+template <int LOGM, int LOGE>
+__global__ __launch_bounds__((1 << (LOGM - LOGE))) void k_moddown_pre(DevTables tb, const uint64_t* d,
+                                                                      const uint64_t* ext1, const uint64_t* evk,
+                                                                      const uint64_t* t2, uint64_t* out, int items2,
+                                                                      EvalIn ev) {
+  using B = BlockNtt<LOGM, LOGE>;
+  extern __shared__ uint64_t lds[];
+  const size_t N = (size_t)1 << tb.log_n;
+  const int R = (int)(N >> LOGM);
+  const Tile tl = xcd_tile(R * tb.ell, items2);
+  if (!tl.valid) return;
+  const int tid = threadIdx.x, b = tl.tile % R;
+  const int i = tl.tile / R;
+  const int item = tl.item >> 1, c = tl.item & 1;
+  const LimbC L = tb.limb[i];
+  const int nl = tb.nl, ell = tb.ell;
+  const size_t boff = (size_t)b * B::M;
+  const int own = i / tb.alpha;
+  double v[B::E];
+  {
+    const uint64_t* src = t2 + (((size_t)item * 2 + c) * ell + i) * N + boff;
+#pragma unroll
+    for (int e = 0; e < B::E; ++e) v[e] = u2d(src[B::fr_pos(tid, e)]);
+  }
+  fwd_opaque<B>(arf(tb, L, i, false), v, reinterpret_cast<double*>(lds), tid, (uint32_t)R + b);
+  double sum[B::E];
+#pragma unroll
+  for (int e = 0; e < B::E; ++e) sum[e] = -v[e];  // |v| <= 2.2q
+  for (int j = 0; j < tb.ndig; ++j) {
+    const uint64_t* src = j == own ? d + ((size_t)item * ell + i) * N + boff
+                                   : ext1 + (((size_t)item * tb.ndig + j) * nl + i) * N + boff;
+    const uint64_t* key = evk + key_row(tb, j, c, i) * N + boff;
+#pragma unroll
+    for (int e = 0; e < B::E; ++e) {
+      const int x = B::cl_pos(tid, e);
+      sum[e] += f_mul(u2d(src[x]), u2d(key[x]), L.qd, L.qinv);  // canonical operands: within 0.875q
+    }
+    if ((j & 3) == 3) {  // 2.2q + 4 * 0.875q stays below 8q <= 2^53
+#pragma unroll
+      for (int e = 0; e < B::E; ++e) sum[e] = f_red(sum[e], L.qd, L.qinv);
+    }
+  }
+  const double pinv = tb.dn_pinv_d[i];
+  const size_t r0 = (((size_t)item * 2 + 0) * ell + i) * N + boff, r1 = (((size_t)item * 2 + 1) * ell + i) * N + boff;
+  const size_t rc = c ? r1 : r0;
+#pragma unroll
+  for (int e = 0; e < B::E; ++e) {
+    const int x = B::cl_pos(tid, e);
+    double o = f_mul(f_red(sum[e], L.qd, L.qinv), pinv, L.qd, L.qinv);
+    if (ev.a) {
+      if (ev.galois) {  // HROT: sigma(c0) joins component 0
+        if (c == 0) o += u2d(ev.a[r0 + x - (boff + x) + galois_src((uint32_t)(boff + x), ev.galois, tb.log_n)]);
+      } else {  // HMUL: a0 b0 to component 0, a0 b1 + a1 b0 to component 1
+        const double a0 = u2d(ev.a[r0 + x]);
+        if (c == 0)
+          o += f_mul(a0, u2d(ev.b[r0 + x]), L.qd, L.qinv);
+        else
+          o += f_mul(a0, u2d(ev.b[r1 + x]), L.qd, L.qinv) + f_mul(u2d(ev.a[r1 + x]), u2d(ev.b[r0 + x]), L.qd, L.qinv);
+      }
+    }
+    __builtin_nontemporal_store(f_canon(o, L.qd, L.qinv), out + rc + x);
+  }
+}
+
 // ------------------------------------------------------ standalone kernels
 
 // ks_modup: forward block pass of every non-digit limb of ext (in place).
@@ -1476,6 +1594,28 @@ struct ModdownKmBlocks {
   }
 };
 template <int LOGM, int LOGE>
+struct KeymultPre {
+  static hipError_t run(const DevTables& tb, const uint64_t* ext1, const uint64_t* evk, uint64_t* acc, int items,
+                        hipStream_t s) {
+    using B = BlockNtt<LOGM, LOGE>;
+    allow_lds<k_keymult_pre<LOGM, LOGE>>();
+    k_keymult_pre<LOGM, LOGE><<<dim3(xcd_grid(tb.k << (tb.log_n - LOGM), 2 * items)), dim3(B::T),
+                                block_lds<LOGM, LOGE>(), s>>>(tb, ext1, evk, acc, 2 * items);
+    return hipGetLastError();
+  }
+};
+template <int LOGM, int LOGE>
+struct ModdownPre {
+  static hipError_t run(const DevTables& tb, const uint64_t* d, const uint64_t* ext1, const uint64_t* evk,
+                        const uint64_t* t2, uint64_t* out, int items, EvalIn ev, hipStream_t s) {
+    using B = BlockNtt<LOGM, LOGE>;
+    allow_lds<k_moddown_pre<LOGM, LOGE>>();
+    k_moddown_pre<LOGM, LOGE><<<dim3(xcd_grid(tb.ell << (tb.log_n - LOGM), 2 * items)), dim3(B::T),
+                                block_lds<LOGM, LOGE>(), s>>>(tb, d, ext1, evk, t2, out, 2 * items, ev);
+    return hipGetLastError();
+  }
+};
+template <int LOGM, int LOGE>
 struct ExtBlocks {
   static hipError_t run(const DevTables& tb, uint64_t* ext, int items, hipStream_t s) {
     using B = BlockNtt<LOGM, LOGE>;
@@ -1575,6 +1715,18 @@ hipError_t launch_moddown_blocks(const DevTables& tb, int log_r, const uint64_t*
 
 hipError_t launch_ext_blocks(const DevTables& tb, int log_r, uint64_t* ext, int items, hipStream_t s) {
   return by_logm<ExtBlocks>(tb.log_n - log_r, (long)(tb.nl << log_r) * items * tb.ndig, tb, ext, items, s);
+}
+
+hipError_t launch_keymult_pre(const DevTables& tb, int log_r, const uint64_t* ext1, const uint64_t* evk,
+                              uint64_t* acc, int items, hipStream_t s) {
+  return by_logm<KeymultPre>(tb.log_n - log_r, (long)(tb.k << log_r) * items * 2, tb, ext1, evk, acc, items, s);
+}
+
+hipError_t launch_moddown_pre(const DevTables& tb, int log_r, const uint64_t* d, const uint64_t* ext1,
+                              const uint64_t* evk, const uint64_t* t2, uint64_t* out, int items, EvalIn ev,
+                              hipStream_t s) {
+  return by_logm<ModdownPre>(tb.log_n - log_r, (long)(tb.ell << log_r) * items * 2, tb, d, ext1, evk, t2, out, items,
+                             ev, s);
 }
 
 hipError_t launch_pblocks_inv(const DevTables& tb, int log_r, const uint64_t* acc, uint64_t* accp, int items,

@@ -45,6 +45,14 @@ hipError_t launch_moddown_blocks(const DevTables& tb, int log_r, const uint64_t*
 hipError_t launch_eval_blocks(const DevTables& tb, int log_r, EvalIn ev, uint64_t* d2, uint64_t* t1, int items,
                               hipStream_t s);
 hipError_t launch_ext_blocks(const DevTables& tb, int log_r, uint64_t* ext, int items, hipStream_t s);
+// Hoisted forward passes (ext1 [items][ndig][nl][N] already forward-transformed by launch_ext_blocks):
+// the P-limb KeyMult and inverse block pass into acc (as K3's finalize), one component per workgroup;
+hipError_t launch_keymult_pre(const DevTables& tb, int log_r, const uint64_t* ext1, const uint64_t* evk,
+                              uint64_t* acc, int items, hipStream_t s);
+// and ModDown's last pass over the Q limbs with their KeyMult (as K5), one component per workgroup.
+hipError_t launch_moddown_pre(const DevTables& tb, int log_r, const uint64_t* d, const uint64_t* ext1,
+                              const uint64_t* evk, const uint64_t* t2, uint64_t* out, int items, EvalIn ev,
+                              hipStream_t s);
 hipError_t launch_pblocks_inv(const DevTables& tb, int log_r, const uint64_t* acc, uint64_t* accp, int items,
                               hipStream_t s);
 hipError_t launch_copy_digits(const DevTables& tb, const uint64_t* d, uint64_t* ext, int items, hipStream_t s);

@@ -49,6 +49,10 @@ def test_candidates_cover_both_bconv_variants():
     split = ks.PLAN_SPLIT_STREAMS
     assert (ks.DPOB, 1, 4, ks.PLAN_MFMA_BCONV | split, 0) in keys
     assert not any(p.flags & split for p in autotune.candidate_plans(P, 1))
+    # the hoisted forward pass is a DPOB candidate only
+    hoist = ks.PLAN_HOIST_FWD
+    assert (ks.DPOB, 1, 4, ks.PLAN_MFMA_BCONV | hoist, 0) in keys
+    assert all(p.dataflow == ks.DPOB for p in plans if p.flags & hoist)
     # batch tiles of B/2 and B/4 for the digit-parallel plans, none below a batch of 4
     assert (ks.DPOB, 1, 4, ks.PLAN_MFMA_BCONV, 4) in keys and (ks.STAGED, 1, 4, 0, 2) in keys
     assert not any(p.batch_tile and p.dataflow not in (ks.DPOB, ks.STAGED) for p in plans)
@@ -84,6 +88,8 @@ def test_table_lookup_exact_then_nearest_batch():
     # flags round-trip through the table
     table[autotune._cache_key(P, 16)] = {"plan": [ks.DPOB, 1, 4, 3], "ms": 1.0, "name": "w"}
     assert autotune.cached_plan(P, 16, table).flags == ks.PLAN_MFMA_BCONV | ks.PLAN_SPLIT_STREAMS
+    table[autotune._cache_key(P, 24)] = {"plan": [ks.DPOB, 1, 4, 5, 0], "ms": 1.0, "name": "h"}
+    assert autotune.cached_plan(P, 24, table).flags == ks.PLAN_MFMA_BCONV | ks.PLAN_HOIST_FWD
     # another parameter set finds nothing
     assert autotune.plan_for(FakeParams(2, 15, 10), 8, table) is None
     # a stored plan the parameters do not accept is skipped

@@ -48,13 +48,14 @@ def test_hmul_and_hrot_match_oracle(ks, dnum, log_n, ell, levels):
         # batches); STAGED runs it as separate kernels
         for plan in (None, ks.make_plan(ks.DPOB, 1, 2, mfma=True), ks.make_plan(ks.DSOC, min(2, level), 3),
                      ks.make_plan(ks.DSOB, 1, 0), ks.make_plan(ks.DPOC, min(2, level), 1, split=True),
-                     ks.make_plan(ks.STAGED), ks.make_plan(ks.DPOB, 1, 2, tile=2), ks.make_plan(ks.STAGED, tile=2)):
+                     ks.make_plan(ks.STAGED), ks.make_plan(ks.DPOB, 1, 2, tile=2), ks.make_plan(ks.STAGED, tile=2),
+                     ks.make_plan(ks.DPOB, 1, 2, mfma=True, hoist=True)):
             out = empty(ref.shape)
             G.hmul(dev(a), dev(b), mk, out, batch, G.eval_workspace(batch, plan), plan)
             assert_same(host(out), ref, f"hmul level {level} {plan}")
         hrot_plans = (ks.make_plan(ks.DPOB, 1, 2, mfma=True), ks.make_plan(ks.DSOC, min(2, level), 3),
                       ks.make_plan(ks.DPOC, min(2, level), 1, split=True), ks.make_plan(ks.STAGED),
-                      ks.make_plan(ks.DPOB, 1, 2, tile=2))
+                      ks.make_plan(ks.DPOB, 1, 2, tile=2), ks.make_plan(ks.DPOB, 1, 2, split=True, hoist=True))
         for gi, g in enumerate((5, 25, 2 * P.n - 1)):
             rk_h = oracle.keygen_pair(Pt, oracle.automorph_coeffs(s, g), s)
             ref = oracle.hrot(P, a, g, rk_h, batch)

@@ -59,7 +59,8 @@ def test_level_keyswitch_every_plan(ks, dnum, log_n, ell, levels):
         dd = dev(d)
         c = min(2, level)  # chunks of the output limbs, at most one per limb
         plans = [None, ks.make_plan(ks.DSOB), ks.make_plan(ks.DPOC, c), ks.make_plan(ks.STAGED),
-                 ks.make_plan(ks.DPOB, 1, 2, mfma=True), ks.make_plan(ks.DSOC, c, 3, mfma=True, split=True)]
+                 ks.make_plan(ks.DPOB, 1, 2, mfma=True), ks.make_plan(ks.DSOC, c, 3, mfma=True, split=True),
+                 ks.make_plan(ks.DPOB, 1, 2, hoist=True)]
         for plan in plans:
             out = empty(ref.shape)
             G.keyswitch(dd, ee, out, batch, G.workspace(batch, plan), plan)

@@ -125,6 +125,9 @@ def _plans(ks, P, log_n):
             plans.append(ks.make_plan(df, chunks, log_r, mfma=True, split=True))
             # passes of 2 + 1 items reusing one workspace, and of 1 item
             plans.append(ks.make_plan(df, chunks, log_r, tile=2))
+            if df == ks.DPOB:  # the raised digits' forward pass as a launch of its own
+                plans.append(ks.make_plan(df, chunks, log_r, hoist=True))
+                plans.append(ks.make_plan(df, chunks, log_r, mfma=True, split=True, hoist=True))
             if log_r == 3:
                 plans.append(ks.make_plan(df, chunks, log_r, mfma=True, split=True, tile=2))
                 plans.append(ks.make_plan(df, chunks, log_r, tile=1))
@@ -167,7 +170,8 @@ def test_keyswitch_benchmark_sizes(ks, name):
     plans = [None, ks.make_plan(ks.DSOB), ks.make_plan(ks.DPOC, 4), ks.make_plan(ks.DSOC, 2),
              ks.make_plan(ks.DPOB, 1, 4, mfma=True), ks.make_plan(ks.DSOC, 3, 3, mfma=True),
              ks.make_plan(ks.STAGED, 1, 4, mfma=True), ks.make_plan(ks.DPOB, 1, 4, mfma=True, split=True),
-             ks.make_plan(ks.DPOB, 1, 5, mfma=True), ks.make_plan(ks.DPOB, 1, 4, mfma=True, tile=3)]
+             ks.make_plan(ks.DPOB, 1, 5, mfma=True), ks.make_plan(ks.DPOB, 1, 4, mfma=True, tile=3),
+             ks.make_plan(ks.DPOB, 1, 4, mfma=True, hoist=True)]
     for plan in plans:
         out = empty(ref.shape)
         ws = G.workspace(batch, plan)
@@ -193,7 +197,8 @@ def test_keyswitch_deep_set_one_ciphertext(ks):
     assert tuned is not None
     dd, ee = dev(d1), dev(evk)
     for plan in (tuned, ks.make_plan(ks.DSOB), None, ks.make_plan(ks.DSOB, 1, 5, mfma=True),
-                 ks.make_plan(ks.DPOC, 4, 4, mfma=True), ks.make_plan(ks.STAGED, 1, 5, mfma=True)):
+                 ks.make_plan(ks.DPOC, 4, 4, mfma=True), ks.make_plan(ks.STAGED, 1, 5, mfma=True),
+                 ks.make_plan(ks.DPOB, 1, 5, mfma=True, hoist=True)):
         out = empty(ref1.shape)
         G.keyswitch(dd, ee, out, 1, G.workspace(1, plan), plan)
         got = host(out)
@@ -276,7 +281,10 @@ def test_argument_errors(ks):
         ks.KsParams(1, 10, 20).workspace_bytes(1, ks.make_plan(ks.DPOB, 1, 2, mfma=True))
     assert e.value.code == ks.KS_EUNSUP
     with pytest.raises(ks.KsError) as e:
-        G.keyswitch(d, evk, out, 1, ws, ks.Plan(ks.DPOB, 1, 2, 6))
+        G.keyswitch(d, evk, out, 1, ws, ks.Plan(ks.DPOB, 1, 2, 8))  # an unknown flag bit
+    assert e.value.code == ks.KS_EUNSUP
+    with pytest.raises(ks.KsError) as e:  # the hoisted forward pass with a dataflow other than DPOB
+        G.keyswitch(d, evk, out, 1, ws, ks.Plan(ks.DSOC, 2, 2, ks.PLAN_HOIST_FWD))
     assert e.value.code == ks.KS_EUNSUP
     with pytest.raises(ks.KsError) as e:
         G.ntt(d, P.nl - 1, 2, 1)
@@ -316,6 +324,10 @@ def test_launch_counts_follow_table_iii(ks):
     # Table III: launches DSOB O(d), DPOB O(1), DSOC O(dc), DPOC O(c)
     G, P = params(ks, 4, 16, 32)
     assert G.launch_count(1, ks.make_plan(ks.DPOB)) == 5 == _expected_launches(P, "DPOB", 1)
+    assert G.launch_count(1, ks.make_plan(ks.DPOB, hoist=True)) == 6  # the raised digits' forward pass on its own
+    with pytest.raises(ks.KsError) as e:  # the hoisted forward pass exists for DPOB only
+        G.workspace_bytes(1, ks.make_plan(ks.DSOB, hoist=True))
+    assert e.value.code == ks.KS_EUNSUP
     assert G.launch_count(1, ks.make_plan(ks.DSOB)) == _expected_launches(P, "DSOB", 1) == 1 + 3 * P.ndig + 2
     for c in (2, 3, 5):
         assert G.launch_count(1, ks.make_plan(ks.DPOC, c)) == _expected_launches(P, "DPOC", c)

@@ -25,7 +25,8 @@ def ks():
 @pytest.mark.parametrize("dnum,log_n,ell,batch,df,flags,tile", [(2, 15, 10, 4, 1, 0, 0), (4, 16, 32, 2, 1, 0, 0),
                                                                  (2, 13, 6, 1, 0, 0, 0), (3, 12, 7, 3, 3, 0, 0),
                                                                  (2, 15, 10, 4, 1, 3, 0), (3, 12, 7, 3, 4, 2, 0),
-                                                                 (2, 15, 10, 5, 1, 3, 2)])
+                                                                 (2, 15, 10, 5, 1, 3, 2), (2, 13, 6, 1, 1, 4, 0),
+                                                                 (3, 12, 7, 3, 1, 7, 0)])
 def test_graph_replay_matches_eager(ks, dnum, log_n, ell, batch, df, flags, tile):
     """Replays of a captured KeySwitch equal eager calls; flags 2 (a batch
     split over two streams) captures a fork and a join of the second stream,
@@ -34,7 +35,7 @@ def test_graph_replay_matches_eager(ks, dnum, log_n, ell, batch, df, flags, tile
     P = oracle.Params(dnum, log_n, ell)
     _, _, evk = oracle.keygen(P, h=64)
     plan = ks.make_plan(df, 2 if df in (ks.DSOC, ks.DPOC) else 1, 3 if flags & 1 else -1,
-                        mfma=bool(flags & 1), split=bool(flags & 2), tile=tile)
+                        mfma=bool(flags & 1), split=bool(flags & 2), tile=tile, hoist=bool(flags & 4))
     ee = dev(evk)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
