@@ -39,8 +39,8 @@ OP_METRIC = {"keyswitch": "KeySwitch/s", "hmul": "HMUL/s", "hrot": "HROT/s"}
 # (sha256 below) and for the same workload and plan; otherwise "traffic" is null.
 # The rocprofv3 summaries it comes from are under profiles/.
 TRAFFIC = {"workload": "d4-n16-l32", "plan": "Plan(DPOB, chunks=1, log_r=4, mfma)", "kernel": "moddown_blocks",
-           "fetch_kib": 467276.3, "fetch_scale": 2.0, "write_kib": 262144.4, "write_scale": 1.0,
-           "sources_sha256": "fd9f553e5eb1e4f3d70372fdaaa5ac76563411d6ab39acc641d2da4de21565b9"}
+           "fetch_kib": 467292.4, "fetch_scale": 2.0, "write_kib": 262145.0, "write_scale": 1.0,
+           "sources_sha256": "b3ff0a69815c593ee6725f96234da0a4136124b4acbe0f294b8cde32fe7a8e9d"}
 TRAFFIC_SOURCES = ["paper_2603_16692_amd/csrc/ks_kernels.hip", "paper_2603_16692_amd/csrc/ks_device.hpp"]
 
 

@@ -378,7 +378,7 @@ def test_extreme_shapes(ks, dnum, log_n, ell, batch):
     d = ciphertext_batch(P.q, P.n, batch)
     _, _, evk = oracle.keygen(P, h=min(64, P.n // 2))
     ref = oracle.keyswitch(P, d, evk, batch)
-    for plan in (None, ks.make_plan(ks.STAGED), ks.make_plan(ks.DSOB)):
+    for plan in (None, ks.make_plan(ks.STAGED), ks.make_plan(ks.DSOB), ks.make_plan(ks.DPOB, hoist=True)):
         out = empty(ref.shape)
         G.keyswitch(dev(d), dev(evk), out, batch, G.workspace(batch, plan), plan)
         assert_same(host(out), ref, f"{(dnum, log_n, ell)} {plan}")
