@@ -38,7 +38,8 @@ OP_METRIC = {"keyswitch": "KeySwitch/s", "hmul": "HMUL/s", "hrot": "HROT/s"}
 # of them. The figure holds only for the kernel sources it was measured on
 # (sha256 below) and for the same workload and plan; otherwise "traffic" is null.
 # The rocprofv3 summaries it comes from are under profiles/.
-TRAFFIC = {"workload": "d4-n16-l32", "plan": "Plan(DPOB, chunks=1, log_r=4, mfma)", "kernel": "moddown_blocks",
+TRAFFIC = {"workload": "d4-n16-l32", "op": "keyswitch", "batch": 8, "plan": "Plan(DPOB, chunks=1, log_r=4, mfma)",
+           "kernel": "moddown_blocks",
            "fetch_kib": 467292.4, "fetch_scale": 2.0, "write_kib": 262145.0, "write_scale": 1.0,
            "sources_sha256": "b3ff0a69815c593ee6725f96234da0a4136124b4acbe0f294b8cde32fe7a8e9d"}
 TRAFFIC_SOURCES = ["paper_2603_16692_amd/csrc/ks_kernels.hip", "paper_2603_16692_amd/csrc/ks_device.hpp"]
@@ -53,10 +54,11 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(workload, plan_repr, kernel):
+def measured_traffic(workload, op, batch, plan_repr, kernel):
     """HBM bytes per launch of `kernel` from the stored counters, or None."""
     t = TRAFFIC
-    if not t or t["workload"] != workload or t["plan"] != plan_repr or t["kernel"] != kernel:
+    if (not t or t["workload"] != workload or t["op"] != op or t["batch"] != batch or t["plan"] != plan_repr
+            or t["kernel"] != kernel):
         return None
     if t["sources_sha256"] != kernel_sources_sha256():
         return None
@@ -466,7 +468,8 @@ def main():
     alg_per_launch = ks_bytes * batch / per_step
     achieved = alg_per_launch / (dom_avg_ms / 1e3) / 1e9
     staged = kernel_bytes(G, plan, batch, dominant)
-    traffic = measured_traffic(args.workload, repr(plan), ks.KIND_NAMES[dominant]) if not args.level else None
+    traffic = (measured_traffic(args.workload, args.op, batch, repr(plan), ks.KIND_NAMES[dominant])
+               if not args.level else None)
     step_GBs = ks_bytes * value / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
