@@ -23,7 +23,7 @@ import statistics
 import torch
 
 from . import (DPOB, DPOC, DSOB, DSOC, STAGED, DATAFLOW_NAMES, HipEvents,
-               KsError, Plan, make_plan)
+               KsError, PLAN_HOIST_FWD, Plan, make_plan)
 
 WORD = 8
 MALL_BYTES = 256 << 20
@@ -255,9 +255,12 @@ def grid_map(batch: int = 1, chunk_range=(2, 4, 8), reps: int = 3, trials: int =
                 best, results = tune(G, d, evk, batch, plans=plans, reps=reps, trials=trials, cache=table)
                 per_df = {}
                 for r in results:
-                    name = DATAFLOW_NAMES[r["plan"][0]]
-                    if r["bit_exact"] and (name not in per_df or r["ms"] < per_df[name]):
-                        per_df[name] = r["ms"]
+                    names = [DATAFLOW_NAMES[r["plan"][0]]]
+                    if r["plan"][3] & PLAN_HOIST_FWD:  # also kept apart: DPOB with the hoisted forward pass
+                        names.append(names[0] + "-hoist")
+                    for name in names:
+                        if r["bit_exact"] and (name not in per_df or r["ms"] < per_df[name]):
+                            per_df[name] = r["ms"]
                 best_ms = next(r["ms"] for r in results if r["plan"] == list(best.key()))
                 row = {"dnum": dnum, "log_n": log_n, "L": ell, "batch": batch, "best": repr(best),
                        "best_ms": best_ms, "per_dataflow_ms": per_df, "plans": len(results),
@@ -276,8 +279,12 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser(description="per-parameter dataflow map over the paper's grid")
     ap.add_argument("--batch", type=int, default=1)
     ap.add_argument("--save-tuned", default="", help="merge the winners into this JSON table")
+    ap.add_argument("--log-n", default="", help="comma-separated subset of the grid's log N values")
     args = ap.parse_args()
     table = load_cache(args.save_tuned) if args.save_tuned else {}
-    grid_map(args.batch, table=table, log=lambda s: print(s, flush=True))
+    grid = dict(PAPER_GRID)
+    if args.log_n:
+        grid["log_n"] = tuple(int(v) for v in args.log_n.split(","))
+    grid_map(args.batch, table=table, grid=grid, log=lambda s: print(s, flush=True))
     if args.save_tuned:
         save_cache(table, args.save_tuned)
