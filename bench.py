@@ -379,19 +379,23 @@ def main():
     ms_per_step = total_ms / args.steps
     value = batch * args.steps / (total_ms / 1e3)
 
-    # plain single-ciphertext path on the same parameters (default plan)
-    plain = None
+    # plain single-ciphertext path on the same parameters (the shipped
+    # one-ciphertext plan of this set if there is one, else the default plan)
+    plain = plain_plan = None
     if batch > 1 and not args.no_plain and args.op == "keyswitch":
+        from paper_2603_16692_amd import autotune
+        p1 = autotune.cached_plan(G, 1, autotune.shipped_cache())
+        plain_plan = repr(p1) if p1 is not None else "default " + repr(G.default_plan(1))
         d1 = d[:1].contiguous()
         out1 = out[:1].contiguous()
-        ws1 = G.workspace(1)
+        ws1 = G.workspace(1, p1)
         for _ in range(3):
-            G.keyswitch(d1, evk, out1, 1, ws1)
+            G.keyswitch(d1, evk, out1, 1, ws1, p1)
         pe = ks.HipEvents(2)
         reps = max(10, args.steps)
         pe.record(0, stream)
         for _ in range(reps):
-            G.keyswitch(d1, evk, out1, 1, ws1)
+            G.keyswitch(d1, evk, out1, 1, ws1, p1)
         pe.record(1, stream)
         torch.cuda.synchronize()
         plain = reps / (pe.elapsed_ms(0, 1) / 1e3)
@@ -548,6 +552,7 @@ def main():
         "config": {"workload": desc, "dnum": dnum, "N": G.n, "L": ell, "level": lv, "k": G.k, "batch": batch,
                    "plan": repr(plan), "launches_per_step": len(kinds)},
         "plain_single_ks_per_s": round(plain, 2) if plain else None,
+        "plain_single_plan": plain_plan,
         "graph_ks_per_s": round(graph_rate, 2) if graph_rate else None,
         "h2d_inclusive": h2d,
         "autotune": tuning,
