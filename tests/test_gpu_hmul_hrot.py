@@ -104,8 +104,8 @@ def test_hmul_hrot_decrypt_at_benchmark_size(ks):
 
 def test_hmul_hrot_headline_set_batch8(ks):
     # (4, 2^16, 32), batch 8, under the shipped plan of this set (DPOB, log_r 4,
-    # int8-MFMA BConv) with the tensor product / automorphism fused, and
-    # under STAGED with them as kernels of their own
+    # int8-MFMA BConv) with the tensor product / automorphism fused, under
+    # STAGED with them as kernels of their own, and under the hoisted DPOB
     from paper_2603_16692_amd import autotune
     dnum, log_n, ell, batch = 4, 16, 32, 8
     G = ks.KsParams(dnum, log_n, ell)
@@ -118,7 +118,8 @@ def test_hmul_hrot_headline_set_batch8(ks):
     da, db, dk = dev(a), dev(b), dev(mk)
     ref = oracle.hmul(P, a, b, mk, batch)
     out = empty(ref.shape)
-    for plan in (shipped, ks.make_plan(ks.STAGED, 1, 4, mfma=True)):
+    plans = (shipped, ks.make_plan(ks.STAGED, 1, 4, mfma=True), ks.make_plan(ks.DPOB, 1, 4, mfma=True, hoist=True))
+    for plan in plans:
         out.zero_()
         G.hmul(da, db, dk, out, batch, G.eval_workspace(batch, plan), plan)
         got = host(out)
@@ -129,7 +130,7 @@ def test_hmul_hrot_headline_set_batch8(ks):
     rk = oracle.keygen_pair(P, oracle.automorph_coeffs(s, g), s)
     ref = oracle.hrot(P, a, g, rk, batch)
     drk = dev(rk)
-    for plan in (shipped, ks.make_plan(ks.STAGED, 1, 4, mfma=True)):
+    for plan in plans:
         out.zero_()
         G.hrot(da, g, drk, out, batch, G.eval_workspace(batch, plan), plan)
         got = host(out)

@@ -38,7 +38,7 @@ def _case(ks, dnum, log_n, ell, batch, seed):
 
 def test_noalloc_equals_keyswitch_on_two_calls(ks):
     plans = [None, ks.make_plan(ks.DPOB, 1, 3, mfma=True), ks.make_plan(ks.STAGED),
-             ks.make_plan(ks.DSOC, 2, 2), ks.make_plan(ks.DPOB, 1, 3, split=True)]
+             ks.make_plan(ks.DSOC, 2, 2), ks.make_plan(ks.DPOB, 1, 3, split=True), ks.make_plan(ks.DPOB, 1, 3, hoist=True)]
     # the larger call first, then a smaller one, which must not see the first call's scratch contents
     big = _case(ks, 2, 15, 10, 4, 7100)
     small = _case(ks, 2, 13, 6, 1, 7200)
