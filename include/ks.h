@@ -278,10 +278,12 @@ void ks_graph_destroy(ks_graph* graph);
 /* Kernel kinds of the launch trace. */
 #define KS_K_INTT_D 0         /* inverse block pass of d (first step of ModUp) */
 #define KS_K_MODUP_COLS 1     /* ModUp: inverse column pass, BConv, forward column pass */
-#define KS_K_KEYMULT_BLOCKS 2 /* forward block pass of the raised digits + KeyMult */
+#define KS_K_KEYMULT_BLOCKS 2 /* forward block pass of the raised digits + KeyMult (KS_PLAN_HOIST_FWD: KeyMult of
+                                 the P limbs and their inverse block pass only) */
 #define KS_K_MODDOWN_COLS 3   /* ModDown: inverse column pass, BConv, forward column pass */
 #define KS_K_MODDOWN_BLOCKS 4 /* forward block pass + subtraction and P^-1 */
-#define KS_K_EXT_BLOCKS 5     /* ks_modup: forward block pass of ext */
+#define KS_K_EXT_BLOCKS 5     /* forward block pass of the raised digits in a launch of its own
+                                 (ks_modup, KS_PLAN_HOIST_FWD) */
 #define KS_K_PBLOCKS_INV 6    /* ks_moddown: inverse block pass of the P limbs */
 #define KS_K_COPY_DIGITS 7    /* ks_modup: digit limbs copied into ext */
 #define KS_K_KEYMULT 8        /* ks_keymult element-wise kernel */
